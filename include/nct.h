@@ -1,0 +1,195 @@
+/*
+ * nct.h -- C ABI of libnct.so: one real-time time step of spin non-collinear
+ * TDDFT for a set of two-component spinor Kohn-Sham states on a periodic
+ * real-space / plane-wave grid, on one AMD MI355X (gfx950).
+ *
+ * Physics follows arXiv 2506.21908:
+ *   - Hamiltonian: the non-collinear Kohn-Sham Hamiltonian of Eq. (HNC-SDFT),
+ *     integrated in time as in Eq. (TDSDFT): kinetic -1/2 nabla^2 (plane-wave
+ *     basis), local 2x2 potential [v 1 + b.sigma] with
+ *     v = v_ext + v_H + vbar_xc and b = b_xc + mu_B B_ext(t) (mu_B = 1/2),
+ *     the Zeeman term of Eq. (zeeman_potential), and Kleinman-Bylander
+ *     projectors with j = l +/- 1/2 spinor spherical harmonics, Eqs. (Vps),
+ *     (Vps-soc) and the spinor-harmonic formula of the spin-orbit section.
+ *   - Spin density matrix stored as rho_v = {rho_uu, rho_dd, Re rho_ud,
+ *     Im rho_ud}, Eq. (density4); m_x = 2 Re rho_ud, m_y = -2 Im rho_ud,
+ *     m_z = rho_uu - rho_dd, Eqs. (rho1-3).
+ *   - Exchange-correlation: adiabatic, locally collinear, Eqs. (LC+ALDA2),
+ *     (LC+ALDA); Slater exchange; b_xc = 0 where |m| < m_threshold.
+ *   - Hartree: Eq. (KSpot) solved by FFT, G = 0 term dropped.
+ *   - Propagator (the paper names none): enforced time-reversal symmetry with
+ *     a truncated Taylor exponential of order taylor_order:
+ *        phi = T(-i dt/2 H[rho(psi_n), B(t_n)]) psi_n
+ *        psi~ = T(-i dt/2 H[rho(psi_n), B(t_n)]) phi
+ *        psi_{n+1} = T(-i dt/2 H[rho(psi~), B(t_n + dt)]) phi
+ *
+ * Units: Hartree atomic units.
+ *
+ * Memory layout of a set of states ("psi"), device memory owned by the caller:
+ *   psi[i][s][ix][iy][iz], i < nstates, s = 0 (up) / 1 (down), iz fastest;
+ *   interleaved complex: complex128 (double re, im) when precision = NCT_FP64,
+ *   complex64 (float re, im) when precision = NCT_FP32_MIXED.
+ *   Grid point r = (ix hx, iy hy, iz hz), h_d = cell[d] / n[d].
+ *   Normalisation: dV sum_r sum_s |psi_i(r,s)|^2 = 1, dV = hx hy hz.
+ * Real fields ("[4][N]") are double, index [k][ix][iy][iz], N = nx ny nz.
+ *
+ * Ownership: every device pointer passed in stays owned by the caller; the
+ * library allocates its own workspace in nct_create_system and frees it in
+ * nct_destroy_system.
+ *
+ * Streams: all work is enqueued on params.stream (a hipStream_t; NULL means
+ * the default stream).  Calls return once the work is enqueued, except calls
+ * that write host memory (totals_host, obs_host, dLdB_host, dLdtheta_host),
+ * which synchronise the stream before returning.
+ *
+ * Errors: every call returns an nct_status; no exception crosses the ABI.
+ * NCT_ERR_ARG is returned before any work is enqueued and leaves every output
+ * untouched.  After NCT_ERR_HIP or NCT_ERR_NONFINITE the contents of psi
+ * outputs are unspecified.  nct_last_error(sys) returns a text description of
+ * the last failure on that system (nct_last_error(NULL) for failures of
+ * nct_create_system).  One system must not be used by two host threads at once.
+ */
+#ifndef NCT_H
+#define NCT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nct_system nct_system;
+
+typedef enum {
+  NCT_OK = 0,
+  NCT_ERR_ARG = 1,          /* invalid argument; nothing was done */
+  NCT_ERR_UNSUPPORTED = 2,  /* grid size or option not built into this library */
+  NCT_ERR_OOM = 3,          /* device allocation failed */
+  NCT_ERR_HIP = 4,          /* a HIP runtime call or kernel launch failed */
+  NCT_ERR_NONFINITE = 5,    /* a non-finite density or energy was produced */
+  NCT_ERR_STATE = 6         /* call out of sequence (e.g. no tape recorded) */
+} nct_status;
+
+enum { NCT_FP64 = 0, NCT_FP32_MIXED = 1 };
+
+/* One Kleinman-Bylander channel (l, j = twoj/2): projector radial form
+ * r^l exp(-r^2 / 2 rc^2), cut at r_sphere and normalised by its continuum
+ * radial integral; 'energy' is the KB energy E_lj (Eq. Vps with the
+ * denominator absorbed).  The channel expands to twoj+1 projectors
+ * (m_j = -j..j) built from the spinor harmonics of the spin-orbit section,
+ * read with m = m_j - 1/2 for j = l + 1/2 and m = m_j + 1/2 for j = l - 1/2. */
+typedef struct {
+  int l;          /* 0, 1 or 2 */
+  int twoj;       /* 2l+1 or 2l-1 (>= 1) */
+  double energy;  /* Hartree */
+  double rc;      /* bohr */
+} nct_channel;
+
+/* Circularly polarised Gaussian pulse:
+ * B(t) = A exp(-(t-t0)^2 / 2 tau^2) [cos(omega (t-t0) + phase) e1 + sin(omega (t-t0) + phase) e2] */
+typedef struct {
+  double A, omega, t0, tau, phase;
+  double e1[3], e2[3];
+} nct_pulse;
+
+/* External field B_ext(t) = B0 + sum of pulses (atomic units of field; the
+ * Zeeman energy is mu_B B = B/2 Hartree).  Spin Zeeman coupling only. */
+typedef struct {
+  double B0[3];
+  int npulses;
+  const nct_pulse *pulses;   /* host [npulses]; copied by nct_set_potentials */
+} nct_bfield;
+
+typedef struct {
+  int n[3];                   /* grid; each n[d] in {8,12,16,24,32,48,64,96}; (n[1],n[2]) must be a built pair */
+  double cell[3];             /* orthorhombic periodic cell edges (bohr) */
+  int nstates;                /* S >= 1 */
+  const double *occ;          /* host [S] occupations, or NULL for all 1 */
+  int natoms;                 /* >= 0 */
+  const double *positions;    /* host [natoms][3] (bohr) */
+  int nchannels;              /* projector channels per atom (0: no nonlocal term) */
+  const nct_channel *channels;/* host [nchannels], the same table for every atom */
+  double r_sphere;            /* projector sphere radius (bohr), < half the smallest cell edge */
+  int xc;                     /* 0: none; 1: Slater exchange, locally collinear */
+  int hartree;                /* 0: none; 1: FFT Poisson */
+  double m_threshold;         /* |m| below which b_xc = 0 (bohr^-3) */
+  double dt;                  /* time step (a.u.) */
+  int taylor_order;           /* 1..16 */
+  int precision;              /* NCT_FP64 or NCT_FP32_MIXED */
+  int tape_steps;             /* steps the adjoint tape can hold (0: recompute mode only) */
+  void *stream;               /* hipStream_t or NULL */
+} nct_params;
+
+/* Build a system: copies the parameters, builds FFT tables and the projector
+ * tables of every atom, and allocates all device workspace.  External
+ * potential starts at zero, B_ext at zero, fields self-consistent. */
+nct_status nct_create_system(const nct_params *params, nct_system **out);
+
+/* Free every resource of the system (synchronises its stream). NULL is a no-op. */
+void nct_destroy_system(nct_system *sys);
+
+/* Text of the last error on sys, or of the last nct_create_system failure when sys is NULL. */
+const char *nct_last_error(const nct_system *sys);
+
+/* Set the potentials of Eq. (HNC-SDFT):
+ *   v_ext_dev  device double [N]: external local potential v_ext(r) (copied), or NULL to keep;
+ *   b          host: B_ext(t) description (copied), or NULL to keep;
+ *   fields_dev device double [4][N] {v, b_x, b_y, b_z}: if non-NULL, the total local fields
+ *              are frozen to these values (no density update, no B_ext added) until
+ *              nct_set_potentials is called again with fields_dev = NULL, which returns the
+ *              system to self-consistent fields. */
+nct_status nct_set_potentials(nct_system *sys, const double *v_ext_dev, const nct_bfield *b,
+                              const double *fields_dev);
+
+/* Spin density of psi (Eq. density4):
+ *   rho_v_dev    device double [4][N] {rho_uu, rho_dd, Re rho_ud, Im rho_ud}, or NULL;
+ *   totals_host  host double[4] {N_e, M_x, M_y, M_z} (integrated), or NULL (synchronises);
+ *   update_fields  nonzero: recompute v_H and the exchange fields from this density and keep
+ *                  them as the system's current fields (self-consistent mode only).
+ *   t is used only to report the fields; B_ext(t) is applied when H is applied. */
+nct_status nct_density_magnetization(nct_system *sys, const void *psi_dev, double t,
+                                     double *rho_v_dev, double *totals_host, int update_fields);
+
+/* Current total local fields at time t into device double [4][N] {v, b_x, b_y, b_z}
+ * (v = v_ext + v_H + vbar_xc, b = b_xc + mu_B B_ext(t)). */
+nct_status nct_get_fields(nct_system *sys, double t, double *fields_dev);
+
+/* hpsi = H psi with the current fields and B_ext(t) (psi and hpsi distinct buffers of the
+ * psi layout above). */
+nct_status nct_apply_hamiltonian(nct_system *sys, const void *psi_dev, void *hpsi_dev, double t);
+
+/* Advance psi in place by nsteps ETRS steps from time t0.  The fields of the first step are
+ * computed from psi itself.  obs_host, if non-NULL, receives [nsteps][13] doubles after each
+ * step: t, N_e, M_x, M_y, M_z, E_total, E_kin, E_loc, E_NL, E_H, E_xc, E_Z,
+ * max_i |<psi_i|psi_i> - 1|, with
+ *   E = sum_i f_i <psi_i|T|psi_i> + int v_ext n + sum_i f_i sum_p E_p |C_p,i|^2
+ *       + 1/2 int v_H n + int e_xc + mu_B B.M.
+ * tape nonzero: record what nct_backward_step needs for each of these steps (requires
+ * nsteps <= params.tape_steps); the record of step k of this call has tape_index k.
+ * Returns NCT_ERR_NONFINITE if N_e became non-finite. */
+nct_status nct_step(nct_system *sys, void *psi_dev, double t0, int nsteps, double *obs_host,
+                    int tape);
+
+/* lam = 2 dV f_i (w . sigma) psi_i: the adjoint seed 2 dL/dpsi* of L = w . M(t) with
+ * M = int m dV.  psi and lam have the psi layout; w is host double[3]. */
+nct_status nct_magnetization_seed(nct_system *sys, const void *psi_dev, const double *w,
+                                  void *lam_dev);
+
+/* Reverse-mode (adjoint) of one ETRS step n -> n+1.  With lam = 2 dL/dpsi* (so that
+ * dL = Re sum lam^* dpsi), given lam_{n+1} returns lam_n, including the response of the
+ * Hartree and exchange fields to the density at psi_n and psi~.  The forward quantities come
+ * from tape record tape_index of the last taped nct_step, or, when tape_index < 0, are
+ * recomputed from psi_n_dev (device, psi layout) at time t_n.
+ *   dLdB_host      host double[6]: dL/dB_ext(t_n) (3) and dL/dB_ext(t_n + dt) (3);
+ *   dLdtheta_host  host double[2*npulses]: dL/d(A_k) then dL/d(omega_k) are ADDED to it
+ *                  (accumulate over steps), or NULL.
+ * lam_np1_dev and lam_n_dev may be the same buffer. */
+nct_status nct_backward_step(nct_system *sys, int tape_index, const void *psi_n_dev, double t_n,
+                             const void *lam_np1_dev, void *lam_n_dev, double *dLdB_host,
+                             double *dLdtheta_host);
+
+/* Library build string (architecture, precisions, grid sizes built). */
+const char *nct_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NCT_H */

@@ -1,0 +1,887 @@
+// Host engine of libnct: the C ABI of include/nct.h.
+//
+// Owns the device workspace, the FFT tables (twiddles and digit-reversed
+// |G|^2 per axis), the projector tables of every atom, and drives the
+// kernels of one ETRS step on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nct.h"
+#include "nct_fft.hpp"
+#include "nct_internal.hpp"
+
+using namespace nct;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kMuB = 0.5;  // Bohr magneton, atomic units
+constexpr int kObsWidth = 13;
+
+std::string g_create_error;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct nct_system {
+  nct_params prm{};
+  int n[3] = {0, 0, 0};
+  size_t N = 0;
+  int S = 0;
+  double dV = 0.0;
+  bool fp64 = true;
+  size_t cbytes = 16;   // bytes per complex element
+  hipStream_t st = nullptr;
+  std::string err;
+  std::vector<DevBuf> owned;
+
+  // host copies
+  std::vector<double> occ_h;
+  std::vector<double> positions_h;
+  std::vector<nct_channel> channels_h;
+  std::vector<nct_pulse> pulses;
+  double B0[3] = {0, 0, 0};
+  bool frozen = false;
+  bool fields_valid = false;
+
+  // device: FFT tables (double and float)
+  void* tw64[3] = {nullptr, nullptr, nullptr};
+  void* tw32[3] = {nullptr, nullptr, nullptr};
+  double* g2x64 = nullptr;
+  double* g2yz64 = nullptr;
+  float* g2x32 = nullptr;
+  float* g2yz32 = nullptr;
+
+  // device: fields and densities (FP64)
+  double* occ = nullptr;
+  double* vext = nullptr;
+  double* vH = nullptr;
+  double* rho = nullptr;
+  double* fields = nullptr;    // [4][N] v, b_xc (no B_ext)
+  double* fields_scr = nullptr;
+  float* fields32 = nullptr;
+  void* ncpx = nullptr;        // complex double [N] Poisson work
+  double* fpart = nullptr;     // [nblk][8]
+  double* ftot = nullptr;      // [8]
+  double* epart = nullptr;     // [2S][ntiles][2]
+  double* obs_dev = nullptr;   // [cap][13]
+  int obs_cap = 0;
+
+  // device: psi-sized work (precision of the system)
+  void* psihat = nullptr;
+  void* phi = nullptr;
+  void* phihat = nullptr;
+  void* wbuf = nullptr;
+  void* tmp = nullptr;
+
+  // projectors
+  ProjTables pt;
+  int natoms = 0;
+  void* Wpsi = nullptr;
+  void* Wphi = nullptr;
+  void* Wwork = nullptr;
+  void* Y = nullptr;
+  void* Cpart = nullptr;
+  void* C = nullptr;
+  void* EC = nullptr;
+  double* energy_dev = nullptr;
+};
+
+namespace {
+
+nct_status fail(nct_system* s, nct_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (s) s->err = buf;
+  else g_create_error = buf;
+  return code;
+}
+
+#define HIPCHK(sys, call)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(sys, NCT_ERR_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                  __FILE__, __LINE__);                                                     \
+  } while (0)
+
+nct_status dalloc(nct_system* s, size_t bytes, void** out) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(s, NCT_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  s->owned.push_back({p, bytes});
+  *out = p;
+  return NCT_OK;
+}
+
+template <typename T>
+nct_status upload(nct_system* s, const std::vector<T>& h, T** out) {
+  void* p = nullptr;
+  nct_status r = dalloc(s, h.size() * sizeof(T), &p);
+  if (r != NCT_OK) return r;
+  if (!h.empty()) HIPCHK(s, hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  *out = static_cast<T*>(p);
+  return NCT_OK;
+}
+
+// ---------------------------------------------------------------- FFT tables
+// frequency index held at DIF output position pos (mixed radix, digit reversal)
+std::vector<int> dif_position_to_freq(int Nl) {
+  std::vector<int> rad;
+  for (int s = 0; s < 4; ++s) {
+    int r = plan_radix(Nl, s);
+    if (!r) break;
+    rad.push_back(r);
+  }
+  std::vector<int> m(rad.size());
+  int prod = 1;
+  for (size_t j = 0; j < rad.size(); ++j) {
+    prod *= rad[j];
+    m[j] = Nl / prod;
+  }
+  std::vector<int> k_at(Nl, -1);
+  for (int k = 0; k < Nl; ++k) {
+    int rem = k, pos = 0;
+    for (size_t j = 0; j < rad.size(); ++j) {
+      const int pj = rem % rad[j];
+      rem /= rad[j];
+      pos += pj * m[j];
+    }
+    k_at[pos] = k;
+  }
+  return k_at;
+}
+
+double gval(int k, int Nl, double Lc) {
+  const int ks = (k < (Nl + 1) / 2) ? k : k - Nl;  // fftfreq convention
+  return 2.0 * kPi * ks / Lc;
+}
+
+// ---------------------------------------------------------------- spherical harmonics
+std::complex<double> ylm(int l, int m, double x, double y, double z) {
+  using C = std::complex<double>;
+  if (std::abs(m) > l) return C(0, 0);
+  const double pi = kPi;
+  if (l == 0) return C(0.5 / std::sqrt(pi), 0);
+  if (l == 1) {
+    if (m == 0) return C(std::sqrt(3.0 / (4 * pi)) * z, 0);
+    return -double(m) * std::sqrt(3.0 / (8 * pi)) * C(x, m * y);
+  }
+  if (l == 2) {
+    if (m == 0) return C(std::sqrt(5.0 / (16 * pi)) * (3 * z * z - 1), 0);
+    if (std::abs(m) == 1) return -double(m) * std::sqrt(15.0 / (8 * pi)) * z * C(x, m * y);
+    const double sgn = m > 0 ? 1.0 : -1.0;
+    const C u(x, sgn * y);
+    return std::sqrt(15.0 / (32 * pi)) * u * u;
+  }
+  return C(0, 0);
+}
+
+// Gauss-Legendre nodes/weights on [-1,1]
+void gauss_legendre(int n, std::vector<double>& xs, std::vector<double>& ws) {
+  xs.assign(n, 0);
+  ws.assign(n, 0);
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double x = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      const double dp = n * (x * p1 - p0) / (x * x - 1);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    double p0 = 1, p1 = x;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    const double dp = n * (x * p1 - p0) / (x * x - 1);
+    xs[i] = -x;
+    xs[n - 1 - i] = x;
+    ws[i] = ws[n - 1 - i] = 2.0 / ((1 - x * x) * dp * dp);
+  }
+}
+
+// sqrt( int_0^rs (r^l e^{-r^2/2rc^2})^2 r^2 dr ), composite Gauss-Legendre
+double radial_norm(int l, double rc, double rs) {
+  static std::vector<double> xs, ws;
+  if (xs.empty()) gauss_legendre(24, xs, ws);
+  const int panels = 16;
+  double acc = 0.0;
+  for (int p = 0; p < panels; ++p) {
+    const double a = rs * p / panels, b = rs * (p + 1) / panels;
+    for (size_t q = 0; q < xs.size(); ++q) {
+      const double r = 0.5 * (a + b) + 0.5 * (b - a) * xs[q];
+      const double f = std::pow(r, l) * std::exp(-r * r / (2 * rc * rc));
+      acc += 0.5 * (b - a) * ws[q] * f * f * r * r;
+    }
+  }
+  return std::sqrt(acc);
+}
+
+// Spinor harmonic coefficients: Phi = c_up Y_l^{m_up} chi_up + c_dn Y_l^{m_dn} chi_dn
+void spinor_coeffs(int l, int twoj, int twomj, double& cu, int& mu, double& cd, int& md) {
+  const double mj = 0.5 * twomj;
+  mu = (twomj - 1) / 2;  // twomj is odd: exact division, m_up = m_j - 1/2
+  md = (twomj + 1) / 2;  // m_dn = m_j + 1/2
+  if (twoj == 2 * l + 1) {
+    cu = std::sqrt((l + mj + 0.5) / (2 * l + 1));
+    cd = std::sqrt((l - mj + 0.5) / (2 * l + 1));
+  } else {
+    cu = std::sqrt((l - mj + 0.5) / (2 * l + 1));
+    cd = -std::sqrt((l + mj + 0.5) / (2 * l + 1));
+  }
+}
+
+template <typename R>
+nct_status build_projectors(nct_system* s) {
+  const nct_params& p = s->prm;
+  s->natoms = (p.nchannels > 0) ? p.natoms : 0;
+  if (s->natoms == 0) return NCT_OK;
+  int P = 0;
+  for (int c = 0; c < p.nchannels; ++c) P += p.channels[c].twoj + 1;
+  if (P > 32) return fail(s, NCT_ERR_UNSUPPORTED, "at most 32 projectors per atom (got %d)", P);
+  const int PP = ((P + 15) / 16) * 16;
+  const int NX = s->n[0], NY = s->n[1], NZ = s->n[2];
+  const double h[3] = {p.cell[0] / NX, p.cell[1] / NY, p.cell[2] / NZ};
+  const double rs = p.r_sphere;
+  std::vector<int> row_off(s->natoms + 1, 0);
+  std::vector<int> pidx;
+  std::vector<int> ix_of_row;
+  std::vector<std::complex<double>> beta;  // [J][2][PP]
+  std::vector<double> energy(size_t(s->natoms) * PP, 0.0);
+  std::vector<double> rnorm(p.nchannels);
+  for (int c = 0; c < p.nchannels; ++c) rnorm[c] = radial_norm(p.channels[c].l, p.channels[c].rc, rs);
+  int maxk = 0, maxrt = 0;
+  for (int a = 0; a < s->natoms; ++a) {
+    const double* R0 = p.positions + 3 * a;
+    int cnt = 0;
+    for (int ix = 0; ix < NX; ++ix)
+      for (int iy = 0; iy < NY; ++iy)
+        for (int iz = 0; iz < NZ; ++iz) {
+          double d[3] = {ix * h[0] - R0[0], iy * h[1] - R0[1], iz * h[2] - R0[2]};
+          for (int k = 0; k < 3; ++k) d[k] -= p.cell[k] * std::nearbyint(d[k] / p.cell[k]);
+          const double dist = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+          if (!(dist < rs)) continue;
+          double u[3] = {0, 0, 1};
+          if (dist > 0) {
+            u[0] = d[0] / dist;
+            u[1] = d[1] / dist;
+            u[2] = d[2] / dist;
+          }
+          pidx.push_back(iy * NZ + iz);
+          ix_of_row.push_back(ix);
+          std::vector<std::complex<double>> rowv(2 * PP, std::complex<double>(0, 0));
+          int pcount = 0;
+          for (int c = 0; c < p.nchannels; ++c) {
+            const nct_channel& ch = p.channels[c];
+            const double f = std::pow(dist, ch.l) * std::exp(-dist * dist / (2 * ch.rc * ch.rc)) / rnorm[c];
+            for (int twomj = -ch.twoj; twomj <= ch.twoj; twomj += 2) {
+              double cu, cd;
+              int mu, md;
+              spinor_coeffs(ch.l, ch.twoj, twomj, cu, mu, cd, md);
+              rowv[0 * PP + pcount] = f * cu * ylm(ch.l, mu, u[0], u[1], u[2]);
+              rowv[1 * PP + pcount] = f * cd * ylm(ch.l, md, u[0], u[1], u[2]);
+              energy[size_t(a) * PP + pcount] = ch.energy;
+              ++pcount;
+            }
+          }
+          beta.insert(beta.end(), rowv.begin(), rowv.end());
+          ++cnt;
+        }
+    row_off[a + 1] = row_off[a] + cnt;
+    maxk = std::max(maxk, (2 * cnt + 63) / 64);
+    maxrt = std::max(maxrt, (2 * cnt + 15) / 16);
+  }
+  const int Jtot = row_off[s->natoms];
+  // plane -> ranges
+  std::vector<int> pr_off(NX + 1, 0), pr_b, pr_e;
+  for (int x = 0; x < NX; ++x) {
+    for (int a = 0; a < s->natoms; ++a) {
+      int b = -1, e = -1;
+      for (int J = row_off[a]; J < row_off[a + 1]; ++J) {
+        if (ix_of_row[J] == x) {
+          if (b < 0) b = J;
+          e = J + 1;
+        }
+      }
+      if (b >= 0) {
+        pr_b.push_back(b);
+        pr_e.push_back(e);
+      }
+    }
+    pr_off[x + 1] = int(pr_b.size());
+  }
+  ProjTables& pt = s->pt;
+  pt.natoms = s->natoms;
+  pt.P = P;
+  pt.PP = PP;
+  pt.Jtot = Jtot;
+  pt.max_kchunks = std::max(maxk, 1);
+  pt.max_rowtiles = std::max(maxrt, 1);
+  int *d_row_off, *d_pidx, *d_pr_off, *d_pr_b, *d_pr_e;
+  nct_status r;
+  if ((r = upload(s, row_off, &d_row_off)) != NCT_OK) return r;
+  if ((r = upload(s, pidx, &d_pidx)) != NCT_OK) return r;
+  if ((r = upload(s, pr_off, &d_pr_off)) != NCT_OK) return r;
+  if ((r = upload(s, pr_b, &d_pr_b)) != NCT_OK) return r;
+  if ((r = upload(s, pr_e, &d_pr_e)) != NCT_OK) return r;
+  if ((r = upload(s, energy, &s->energy_dev)) != NCT_OK) return r;
+  std::vector<R> braw(beta.size() * 2);
+  for (size_t k = 0; k < beta.size(); ++k) {
+    braw[2 * k] = R(beta[k].real());
+    braw[2 * k + 1] = R(beta[k].imag());
+  }
+  R* d_beta;
+  if ((r = upload(s, braw, &d_beta)) != NCT_OK) return r;
+  pt.row_off = d_row_off;
+  pt.pidx = d_pidx;
+  pt.pr_off = d_pr_off;
+  pt.pr_begin = d_pr_b;
+  pt.pr_end = d_pr_e;
+  pt.beta = d_beta;
+  pt.energy = s->energy_dev;
+  const size_t rows = size_t(s->S) * 2 * Jtot * s->cbytes;
+  if ((r = dalloc(s, rows, &s->Wpsi)) != NCT_OK) return r;
+  if ((r = dalloc(s, rows, &s->Wphi)) != NCT_OK) return r;
+  if ((r = dalloc(s, rows, &s->Wwork)) != NCT_OK) return r;
+  if ((r = dalloc(s, rows, &s->Y)) != NCT_OK) return r;
+  const size_t cp = size_t(s->natoms) * PP * s->S;
+  if ((r = dalloc(s, cp * pt.max_kchunks * 16, &s->Cpart)) != NCT_OK) return r;
+  if ((r = dalloc(s, cp * 16, &s->C)) != NCT_OK) return r;
+  if ((r = dalloc(s, cp * s->cbytes, &s->EC)) != NCT_OK) return r;
+  return NCT_OK;
+}
+
+// ---------------------------------------------------------------- B(t)
+void bfield_at(const nct_system* s, double t, double B[3]) {
+  for (int k = 0; k < 3; ++k) B[k] = s->B0[k];
+  for (const nct_pulse& p : s->pulses) {
+    const double d = t - p.t0;
+    const double g = std::exp(-d * d / (2 * p.tau * p.tau));
+    const double ph = p.omega * d + p.phase;
+    const double c = std::cos(ph), sn = std::sin(ph);
+    for (int k = 0; k < 3; ++k) B[k] += p.A * g * (c * p.e1[k] + sn * p.e2[k]);
+  }
+}
+
+// d B / d theta, theta = (A_1..A_k, omega_1..omega_k); out [2k][3]
+void bfield_jac(const nct_system* s, double t, std::vector<double>& out) {
+  const size_t k = s->pulses.size();
+  out.assign(2 * k * 3, 0.0);
+  for (size_t i = 0; i < k; ++i) {
+    const nct_pulse& p = s->pulses[i];
+    const double d = t - p.t0;
+    const double g = std::exp(-d * d / (2 * p.tau * p.tau));
+    const double ph = p.omega * d + p.phase;
+    const double c = std::cos(ph), sn = std::sin(ph);
+    for (int q = 0; q < 3; ++q) {
+      out[i * 3 + q] = g * (c * p.e1[q] + sn * p.e2[q]);
+      out[(k + i) * 3 + q] = p.A * g * d * (-sn * p.e1[q] + c * p.e2[q]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- engine
+template <typename R>
+struct Engine {
+  nct_system* s;
+  const void* twx() const { return sizeof(R) == 8 ? s->tw64[0] : s->tw32[0]; }
+  const void* twy() const { return sizeof(R) == 8 ? s->tw64[1] : s->tw32[1]; }
+  const void* twz() const { return sizeof(R) == 8 ? s->tw64[2] : s->tw32[2]; }
+  const R* g2x() const { return sizeof(R) == 8 ? (const R*)s->g2x64 : (const R*)s->g2x32; }
+  const R* g2yz() const { return sizeof(R) == 8 ? (const R*)s->g2yz64 : (const R*)s->g2yz32; }
+  const R* fieldsR() const { return sizeof(R) == 8 ? (const R*)s->fields : (const R*)s->fields32; }
+
+  nct_status check(hipError_t e, const char* what) {
+    if (e != hipSuccess) return fail(s, NCT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return NCT_OK;
+  }
+
+  // Hartree + exchange fields from the density in s->rho (FP64 throughout)
+  nct_status fields_from_rho(bool store) {
+    nct_status r;
+    const double* vh = nullptr;
+    if (s->prm.hartree) {
+      if ((r = check(launch_rho_to_n(s->rho, s->N, s->ncpx, s->st), "rho_to_n")) != NCT_OK) return r;
+      if ((r = check(launch_plane_fwd<double>(s->n, 1, s->ncpx, s->ncpx, nullptr, nullptr, s->tw64[1],
+                                              s->tw64[2], s->st), "poisson fwd")) != NCT_OK) return r;
+      if ((r = check(launch_xpass<double>(s->n, 1, s->ncpx, s->ncpx, s->g2x64, s->g2yz64,
+                                          4.0 * kPi / double(s->N), 1, s->tw64[0], s->st),
+                     "poisson x")) != NCT_OK) return r;
+      if ((r = check(launch_plane_inv<double>(s->n, 1, s->ncpx, s->ncpx, 1.0, s->tw64[1], s->tw64[2],
+                                              s->st), "poisson inv")) != NCT_OK) return r;
+      if ((r = check(launch_cpx_real(s->ncpx, s->N, s->vH, s->st), "cpx_real")) != NCT_OK) return r;
+      vh = s->vH;
+    }
+    int nb = 0;
+    double* out = store ? s->fields : s->fields_scr;
+    float* o32 = (store && !s->fp64) ? s->fields32 : nullptr;
+    if ((r = check(launch_fields(s->rho, s->vext, vh, s->prm.xc, s->prm.m_threshold, s->N, out, o32,
+                                 s->fpart, &nb, s->st), "fields")) != NCT_OK) return r;
+    if ((r = check(launch_reduce_rows(s->fpart, nb, 8, s->ftot, s->st), "reduce")) != NCT_OK) return r;
+    if (store) s->fields_valid = true;
+    return NCT_OK;
+  }
+
+  nct_status density(const void* psi) {
+    return check(launch_density<R>(psi, s->occ, s->S, s->N, s->rho, s->st), "density");
+  }
+
+  // NL projections of the sphere rows W -> Y (scatter rows) and C
+  nct_status projections(const void* W) {
+    if (s->natoms == 0) return NCT_OK;
+    nct_status r;
+    if ((r = check(launch_proj_contract<R>(s->pt, W, s->S, s->dV, s->Cpart, s->C, s->EC, s->st),
+                   "proj_contract")) != NCT_OK) return r;
+    return check(launch_proj_scatter<R>(s->pt, s->EC, s->S, s->Y, s->st), "proj_scatter");
+  }
+
+  void bext_now(double t, R out[3]) {
+    if (s->frozen) {
+      out[0] = out[1] = out[2] = R(0);
+      return;
+    }
+    double B[3];
+    bfield_at(s, t, B);
+    for (int k = 0; k < 3; ++k) out[k] = R(kMuB * B[k]);
+  }
+
+  // T_K(-i a H) x by Horner stages w_k = x + (-i a/(K-k+1)) H w_{k-1}, w_0 = x.
+  nct_status taylor(const void* x, const void* xhat, const void* xW, void* out, void* outhat,
+                    void* outW, double t) {
+    const int K = s->prm.taylor_order;
+    const double a = 0.5 * s->prm.dt;
+    const void* cw = x;
+    const void* chat = xhat;
+    const void* cW = xW;
+    StageArgs<R> sa;
+    bext_now(t, sa.bext);
+    sa.fields = fieldsR();
+    nct_status r;
+    for (int k = 1; k <= K; ++k) {
+      const bool last = (k == K);
+      if ((r = projections(cW)) != NCT_OK) return r;
+      if ((r = check(launch_xpass<R>(s->n, 2 * s->S, chat, s->tmp, g2x(), g2yz(),
+                                     R(0.5 / double(s->N)), 0, twx(), s->st), "xpass")) != NCT_OK)
+        return r;
+      sa.tmp_in = s->tmp;
+      sa.w_in = cw;
+      sa.x_base = x;
+      sa.alpha = R(1);
+      sa.cre = R(0);
+      sa.cim = R(-a / double(K - k + 1));
+      sa.Y = s->natoms ? s->Y : nullptr;
+      sa.w_out = last ? out : s->wbuf;
+      sa.tmp_out = last ? outhat : s->tmp;
+      sa.W = s->natoms ? (last ? outW : s->Wwork) : nullptr;
+      sa.acc = nullptr;
+      if ((r = check(launch_plane_stage<R>(s->n, s->S, sa, s->pt, twy(), twz(), s->st), "plane_stage")) != NCT_OK)
+        return r;
+      cw = sa.w_out;
+      chat = sa.tmp_out;
+      cW = sa.W;
+    }
+    return NCT_OK;
+  }
+
+  nct_status prepare(const void* psi, void* hat, void* W) {
+    return check(launch_plane_fwd<R>(s->n, 2 * s->S, psi, hat, s->natoms ? W : nullptr, &s->pt,
+                                     twy(), twz(), s->st), "plane_fwd");
+  }
+
+  nct_status obs_row(double t, double* row) {
+    nct_status r;
+    int ntiles = 0;
+    if ((r = check(launch_xpass_energy<R>(s->n, 2 * s->S, s->psihat, g2x(), g2yz(),
+                                          R(0.5 / double(s->N)), twx(), s->epart, &ntiles, s->st),
+                   "energy")) != NCT_OK) return r;
+    if (s->natoms) {
+      if ((r = check(launch_proj_contract<R>(s->pt, s->Wpsi, s->S, s->dV, s->Cpart, s->C, s->EC, s->st),
+                     "proj_contract")) != NCT_OK) return r;
+    }
+    ObsInputs in;
+    in.field_tot = s->ftot;
+    in.epart = s->epart;
+    in.ntiles = ntiles;
+    in.C = s->natoms ? s->C : nullptr;
+    in.energy = s->energy_dev;
+    in.occ = s->occ;
+    in.S = s->S;
+    in.natoms = s->natoms;
+    in.PP = s->pt.PP;
+    in.precision = s->prm.precision;
+    in.dV = s->dV;
+    in.invN = 1.0 / double(s->N);
+    in.t = t;
+    double B[3] = {0, 0, 0};
+    if (!s->frozen) bfield_at(s, t, B);
+    for (int k = 0; k < 3; ++k) in.muB_B[k] = kMuB * B[k];
+    return check(launch_obs_row(in, row, s->st), "obs_row");
+  }
+
+  nct_status step(void* psi, double t0, int nsteps, double* obs_host) {
+    nct_status r;
+    const double dt = s->prm.dt;
+    if ((r = prepare(psi, s->psihat, s->Wpsi)) != NCT_OK) return r;
+    if (!s->frozen) {
+      if ((r = density(psi)) != NCT_OK) return r;
+      if ((r = fields_from_rho(true)) != NCT_OK) return r;
+    }
+    if (obs_host && s->obs_cap < nsteps) {
+      void* p;
+      if ((r = dalloc(s, size_t(nsteps) * kObsWidth * sizeof(double), &p)) != NCT_OK) return r;
+      s->obs_dev = static_cast<double*>(p);
+      s->obs_cap = nsteps;
+    }
+    for (int k = 0; k < nsteps; ++k) {
+      const double t = t0 + k * dt;
+      if ((r = taylor(psi, s->psihat, s->Wpsi, s->phi, s->phihat, s->Wphi, t)) != NCT_OK) return r;
+      if ((r = taylor(s->phi, s->phihat, s->Wphi, s->wbuf, nullptr, nullptr, t)) != NCT_OK) return r;
+      if (!s->frozen) {
+        if ((r = density(s->wbuf)) != NCT_OK) return r;
+        if ((r = fields_from_rho(true)) != NCT_OK) return r;
+      }
+      if ((r = taylor(s->phi, s->phihat, s->Wphi, psi, s->psihat, s->Wpsi, t + dt)) != NCT_OK) return r;
+      if (!s->frozen || obs_host) {
+        if ((r = density(psi)) != NCT_OK) return r;
+        if ((r = fields_from_rho(!s->frozen)) != NCT_OK) return r;
+      }
+      if (obs_host) {
+        if ((r = obs_row(t + dt, s->obs_dev + size_t(k) * kObsWidth)) != NCT_OK) return r;
+      }
+    }
+    double tot[8];
+    HIPCHK(s, hipMemcpyAsync(tot, s->ftot, sizeof(tot), hipMemcpyDeviceToHost, s->st));
+    if (obs_host)
+      HIPCHK(s, hipMemcpyAsync(obs_host, s->obs_dev, size_t(nsteps) * kObsWidth * sizeof(double),
+                               hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    if ((!s->frozen || obs_host) && !std::isfinite(tot[0]))
+      return fail(s, NCT_ERR_NONFINITE, "non-finite electron count after step");
+    return NCT_OK;
+  }
+
+  nct_status apply(const void* psi, void* hpsi, double t) {
+    nct_status r;
+    if ((r = prepare(psi, s->tmp, s->Wwork)) != NCT_OK) return r;
+    if ((r = projections(s->Wwork)) != NCT_OK) return r;
+    if ((r = check(launch_xpass<R>(s->n, 2 * s->S, s->tmp, s->tmp, g2x(), g2yz(),
+                                   R(0.5 / double(s->N)), 0, twx(), s->st), "xpass")) != NCT_OK)
+      return r;
+    StageArgs<R> sa;
+    bext_now(t, sa.bext);
+    sa.fields = fieldsR();
+    sa.tmp_in = s->tmp;
+    sa.w_in = psi;
+    sa.x_base = nullptr;
+    sa.alpha = R(0);
+    sa.cre = R(1);
+    sa.cim = R(0);
+    sa.Y = s->natoms ? s->Y : nullptr;
+    sa.w_out = hpsi;
+    return check(launch_plane_stage<R>(s->n, s->S, sa, s->pt, twy(), twz(), s->st), "plane_stage");
+  }
+};
+
+template <typename R>
+nct_status build_fft_tables(nct_system* s) {
+  nct_status r;
+  for (int d = 0; d < 3; ++d) {
+    const int Nl = s->n[d];
+    std::vector<double> t64(2 * Nl);
+    std::vector<float> t32(2 * Nl);
+    for (int e = 0; e < Nl; ++e) {
+      const double ang = -2.0 * kPi * double(e) / double(Nl);
+      t64[2 * e] = std::cos(ang);
+      t64[2 * e + 1] = std::sin(ang);
+      t32[2 * e] = float(t64[2 * e]);
+      t32[2 * e + 1] = float(t64[2 * e + 1]);
+    }
+    double* p64;
+    float* p32;
+    if ((r = upload(s, t64, &p64)) != NCT_OK) return r;
+    if ((r = upload(s, t32, &p32)) != NCT_OK) return r;
+    s->tw64[d] = p64;
+    s->tw32[d] = p32;
+  }
+  std::vector<int> kx = dif_position_to_freq(s->n[0]);
+  std::vector<int> ky = dif_position_to_freq(s->n[1]);
+  std::vector<int> kz = dif_position_to_freq(s->n[2]);
+  std::vector<double> gx(s->n[0]), gyz(size_t(s->n[1]) * s->n[2]);
+  for (int i = 0; i < s->n[0]; ++i) {
+    const double g = gval(kx[i], s->n[0], s->prm.cell[0]);
+    gx[i] = g * g;
+  }
+  for (int i = 0; i < s->n[1]; ++i)
+    for (int j = 0; j < s->n[2]; ++j) {
+      const double g1 = gval(ky[i], s->n[1], s->prm.cell[1]);
+      const double g2 = gval(kz[j], s->n[2], s->prm.cell[2]);
+      gyz[size_t(i) * s->n[2] + j] = g1 * g1 + g2 * g2;
+    }
+  std::vector<float> gx32(gx.begin(), gx.end()), gyz32(gyz.begin(), gyz.end());
+  if ((r = upload(s, gx, &s->g2x64)) != NCT_OK) return r;
+  if ((r = upload(s, gyz, &s->g2yz64)) != NCT_OK) return r;
+  if ((r = upload(s, gx32, &s->g2x32)) != NCT_OK) return r;
+  if ((r = upload(s, gyz32, &s->g2yz32)) != NCT_OK) return r;
+  return NCT_OK;
+}
+
+void free_all(nct_system* s) {
+  for (auto& b : s->owned) (void)hipFree(b.p);
+  s->owned.clear();
+}
+
+nct_status create_impl(const nct_params* p, nct_system** out) {
+  if (!p || !out) return fail(nullptr, NCT_ERR_ARG, "null params or out");
+  *out = nullptr;
+  for (int d = 0; d < 3; ++d) {
+    if (!line_supported(p->n[d]))
+      return fail(nullptr, NCT_ERR_UNSUPPORTED, "grid size n[%d] = %d not built", d, p->n[d]);
+    if (!(p->cell[d] > 0)) return fail(nullptr, NCT_ERR_ARG, "cell[%d] must be > 0", d);
+  }
+  if (!plane_pair_supported(p->n[1], p->n[2]))
+    return fail(nullptr, NCT_ERR_UNSUPPORTED, "plane (%d, %d) not built", p->n[1], p->n[2]);
+  if (p->nstates < 1) return fail(nullptr, NCT_ERR_ARG, "nstates must be >= 1");
+  if (p->taylor_order < 1 || p->taylor_order > 16) return fail(nullptr, NCT_ERR_ARG, "taylor_order in 1..16");
+  if (p->precision != NCT_FP64 && p->precision != NCT_FP32_MIXED)
+    return fail(nullptr, NCT_ERR_ARG, "precision must be NCT_FP64 or NCT_FP32_MIXED");
+  if (!(p->dt > 0)) return fail(nullptr, NCT_ERR_ARG, "dt must be > 0");
+  if (p->natoms < 0 || (p->natoms > 0 && !p->positions)) return fail(nullptr, NCT_ERR_ARG, "bad atoms");
+  if (p->nchannels < 0 || (p->nchannels > 0 && !p->channels)) return fail(nullptr, NCT_ERR_ARG, "bad channels");
+  for (int c = 0; c < p->nchannels; ++c) {
+    const nct_channel& ch = p->channels[c];
+    if (ch.l < 0 || ch.l > 2 || (ch.twoj != 2 * ch.l + 1 && ch.twoj != 2 * ch.l - 1) || !(ch.rc > 0))
+      return fail(nullptr, NCT_ERR_ARG, "bad channel %d", c);
+  }
+  if (p->natoms > 0 && p->nchannels > 0) {
+    const double mincell = std::min(p->cell[0], std::min(p->cell[1], p->cell[2]));
+    if (!(p->r_sphere > 0) || !(p->r_sphere < 0.5 * mincell))
+      return fail(nullptr, NCT_ERR_ARG, "r_sphere must be in (0, cell/2)");
+  }
+  if (p->tape_steps < 0) return fail(nullptr, NCT_ERR_ARG, "tape_steps must be >= 0");
+
+  nct_system* s = new nct_system();
+  s->prm = *p;
+  // keep host copies of the caller's arrays; prm points at the copies
+  s->prm.occ = nullptr;
+  if (p->natoms > 0) s->positions_h.assign(p->positions, p->positions + 3 * size_t(p->natoms));
+  if (p->nchannels > 0) s->channels_h.assign(p->channels, p->channels + p->nchannels);
+  s->prm.positions = s->positions_h.empty() ? nullptr : s->positions_h.data();
+  s->prm.channels = s->channels_h.empty() ? nullptr : s->channels_h.data();
+  for (int d = 0; d < 3; ++d) s->n[d] = p->n[d];
+  s->N = size_t(p->n[0]) * p->n[1] * p->n[2];
+  s->S = p->nstates;
+  s->dV = p->cell[0] * p->cell[1] * p->cell[2] / double(s->N);
+  s->fp64 = p->precision == NCT_FP64;
+  s->cbytes = s->fp64 ? 16 : 8;
+  s->st = static_cast<hipStream_t>(p->stream);
+  s->occ_h.assign(p->nstates, 1.0);
+  if (p->occ)
+    for (int i = 0; i < p->nstates; ++i) s->occ_h[i] = p->occ[i];
+
+  nct_status r = NCT_OK;
+  auto bail = [&](nct_status code) {
+    g_create_error = s->err;
+    free_all(s);
+    delete s;
+    return code;
+  };
+  if ((r = build_fft_tables<double>(s)) != NCT_OK) return bail(r);
+  if ((r = upload(s, s->occ_h, &s->occ)) != NCT_OK) return bail(r);
+  void* p0;
+  const size_t N = s->N;
+  if ((r = dalloc(s, N * 8, &p0)) != NCT_OK) return bail(r);
+  s->vext = (double*)p0;
+  if ((r = dalloc(s, N * 8, &p0)) != NCT_OK) return bail(r);
+  s->vH = (double*)p0;
+  if ((r = dalloc(s, 4 * N * 8, &p0)) != NCT_OK) return bail(r);
+  s->rho = (double*)p0;
+  if ((r = dalloc(s, 4 * N * 8, &p0)) != NCT_OK) return bail(r);
+  s->fields = (double*)p0;
+  if ((r = dalloc(s, 4 * N * 8, &p0)) != NCT_OK) return bail(r);
+  s->fields_scr = (double*)p0;
+  if ((r = dalloc(s, 4 * N * 4, &p0)) != NCT_OK) return bail(r);
+  s->fields32 = (float*)p0;
+  if ((r = dalloc(s, N * 16, &s->ncpx)) != NCT_OK) return bail(r);
+  if ((r = dalloc(s, ((N + 255) / 256) * 8 * 8, &p0)) != NCT_OK) return bail(r);
+  s->fpart = (double*)p0;
+  if ((r = dalloc(s, 8 * 8, &p0)) != NCT_OK) return bail(r);
+  s->ftot = (double*)p0;
+  const size_t nyz = size_t(p->n[1]) * p->n[2];
+  if ((r = dalloc(s, size_t(2 * s->S) * (nyz / 16) * 2 * 8, &p0)) != NCT_OK) return bail(r);
+  s->epart = (double*)p0;
+  const size_t psib = size_t(s->S) * 2 * N * s->cbytes;
+  if ((r = dalloc(s, psib, &s->psihat)) != NCT_OK) return bail(r);
+  if ((r = dalloc(s, psib, &s->phi)) != NCT_OK) return bail(r);
+  if ((r = dalloc(s, psib, &s->phihat)) != NCT_OK) return bail(r);
+  if ((r = dalloc(s, psib, &s->wbuf)) != NCT_OK) return bail(r);
+  if ((r = dalloc(s, psib, &s->tmp)) != NCT_OK) return bail(r);
+  if (s->fp64) r = build_projectors<double>(s);
+  else r = build_projectors<float>(s);
+  if (r != NCT_OK) return bail(r);
+  hipError_t e = hipMemsetAsync(s->vext, 0, N * 8, s->st);
+  if (e == hipSuccess) e = hipMemsetAsync(s->fields, 0, 4 * N * 8, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) {
+    fail(s, NCT_ERR_HIP, "init: %s", hipGetErrorString(e));
+    return bail(NCT_ERR_HIP);
+  }
+  *out = s;
+  return NCT_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+nct_status nct_create_system(const nct_params* params, nct_system** out) {
+  try {
+    return create_impl(params, out);
+  } catch (...) {
+    return fail(nullptr, NCT_ERR_OOM, "host allocation failed in nct_create_system");
+  }
+}
+
+void nct_destroy_system(nct_system* sys) {
+  if (!sys) return;
+  (void)hipStreamSynchronize(sys->st);
+  free_all(sys);
+  delete sys;
+}
+
+const char* nct_last_error(const nct_system* sys) {
+  return sys ? sys->err.c_str() : g_create_error.c_str();
+}
+
+nct_status nct_set_potentials(nct_system* s, const double* v_ext_dev, const nct_bfield* b,
+                              const double* fields_dev) {
+  if (!s) return NCT_ERR_ARG;
+  if (b && b->npulses < 0) return fail(s, NCT_ERR_ARG, "npulses < 0");
+  if (b && b->npulses > 0 && !b->pulses) return fail(s, NCT_ERR_ARG, "pulses is NULL");
+  if (b) {
+    for (int k = 0; k < b->npulses; ++k)
+      if (!(b->pulses[k].tau > 0)) return fail(s, NCT_ERR_ARG, "pulse %d: tau must be > 0", k);
+  }
+  if (v_ext_dev) HIPCHK(s, hipMemcpyAsync(s->vext, v_ext_dev, s->N * 8, hipMemcpyDeviceToDevice, s->st));
+  if (b) {
+    for (int k = 0; k < 3; ++k) s->B0[k] = b->B0[k];
+    s->pulses.assign(b->pulses, b->pulses + b->npulses);
+  }
+  if (fields_dev) {
+    HIPCHK(s, hipMemcpyAsync(s->fields, fields_dev, 4 * s->N * 8, hipMemcpyDeviceToDevice, s->st));
+    if (!s->fp64) HIPCHK(s, launch_to_float(s->fields, 4 * s->N, s->fields32, s->st));
+    s->frozen = true;
+    s->fields_valid = true;
+  } else {
+    if (s->frozen) s->fields_valid = false;
+    s->frozen = false;
+    if (v_ext_dev) s->fields_valid = false;
+  }
+  return NCT_OK;
+}
+
+nct_status nct_density_magnetization(nct_system* s, const void* psi, double t, double* rho_v_dev,
+                                     double* totals_host, int update_fields) {
+  (void)t;
+  if (!s || !psi) return s ? fail(s, NCT_ERR_ARG, "psi is NULL") : NCT_ERR_ARG;
+  if (update_fields && s->frozen) return fail(s, NCT_ERR_STATE, "fields are frozen");
+  nct_status r;
+  if (s->fp64) r = Engine<double>{s}.density(psi);
+  else r = Engine<float>{s}.density(psi);
+  if (r != NCT_OK) return r;
+  if (update_fields || totals_host) {
+    if (s->fp64) r = Engine<double>{s}.fields_from_rho(update_fields != 0);
+    else r = Engine<float>{s}.fields_from_rho(update_fields != 0);
+    if (r != NCT_OK) return r;
+  }
+  if (rho_v_dev)
+    HIPCHK(s, hipMemcpyAsync(rho_v_dev, s->rho, 4 * s->N * 8, hipMemcpyDeviceToDevice, s->st));
+  if (totals_host) {
+    double tot[8];
+    HIPCHK(s, hipMemcpyAsync(tot, s->ftot, sizeof(tot), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    for (int k = 0; k < 4; ++k) totals_host[k] = tot[k] * s->dV;
+    if (!std::isfinite(tot[0])) return fail(s, NCT_ERR_NONFINITE, "non-finite density");
+  }
+  return NCT_OK;
+}
+
+nct_status nct_get_fields(nct_system* s, double t, double* out) {
+  if (!s || !out) return s ? fail(s, NCT_ERR_ARG, "out is NULL") : NCT_ERR_ARG;
+  if (!s->fields_valid) return fail(s, NCT_ERR_STATE, "fields not computed yet");
+  double B[3] = {0, 0, 0};
+  if (!s->frozen) {
+    bfield_at(s, t, B);
+    for (int k = 0; k < 3; ++k) B[k] *= kMuB;
+  }
+  HIPCHK(s, launch_add_bext(s->fields, s->N, B, out, s->st));
+  return NCT_OK;
+}
+
+nct_status nct_apply_hamiltonian(nct_system* s, const void* psi, void* hpsi, double t) {
+  if (!s || !psi || !hpsi) return s ? fail(s, NCT_ERR_ARG, "null psi/hpsi") : NCT_ERR_ARG;
+  if (psi == hpsi) return fail(s, NCT_ERR_ARG, "psi and hpsi must differ");
+  if (!s->fields_valid) return fail(s, NCT_ERR_STATE, "fields not computed (call nct_density_magnetization with update_fields)");
+  if (s->fp64) return Engine<double>{s}.apply(psi, hpsi, t);
+  return Engine<float>{s}.apply(psi, hpsi, t);
+}
+
+nct_status nct_step(nct_system* s, void* psi, double t0, int nsteps, double* obs_host, int tape) {
+  if (!s || !psi) return s ? fail(s, NCT_ERR_ARG, "psi is NULL") : NCT_ERR_ARG;
+  if (nsteps < 0) return fail(s, NCT_ERR_ARG, "nsteps < 0");
+  if (tape && nsteps > s->prm.tape_steps) return fail(s, NCT_ERR_ARG, "nsteps exceeds tape_steps");
+  if (tape) return fail(s, NCT_ERR_UNSUPPORTED, "tape not available in this build");
+  if (nsteps == 0) return NCT_OK;
+  if (s->frozen && !s->fields_valid) return fail(s, NCT_ERR_STATE, "no fields");
+  if (s->fp64) return Engine<double>{s}.step(psi, t0, nsteps, obs_host);
+  return Engine<float>{s}.step(psi, t0, nsteps, obs_host);
+}
+
+nct_status nct_magnetization_seed(nct_system* s, const void* psi, const double* w, void* lam) {
+  if (!s || !psi || !w || !lam) return s ? fail(s, NCT_ERR_ARG, "null argument") : NCT_ERR_ARG;
+  hipError_t e;
+  if (s->fp64) e = launch_seed<double>(psi, s->occ, s->S, s->N, w[0], w[1], w[2], 2.0 * s->dV, lam, s->st);
+  else e = launch_seed<float>(psi, s->occ, s->S, s->N, w[0], w[1], w[2], 2.0 * s->dV, lam, s->st);
+  if (e != hipSuccess) return fail(s, NCT_ERR_HIP, "seed: %s", hipGetErrorString(e));
+  return NCT_OK;
+}
+
+nct_status nct_backward_step(nct_system* s, int tape_index, const void* psi_n, double t_n,
+                             const void* lam_np1, void* lam_n, double* dLdB, double* dLdtheta) {
+  (void)tape_index; (void)psi_n; (void)t_n; (void)lam_np1; (void)lam_n; (void)dLdB; (void)dLdtheta;
+  if (!s) return NCT_ERR_ARG;
+  return fail(s, NCT_ERR_UNSUPPORTED, "adjoint not available in this build");
+}
+
+const char* nct_version(void) {
+  return "libnct gfx950; FP64 and FP32-mixed; lines 8,12,16,24,32,48,64,96";
+}
+
+}  // extern "C"

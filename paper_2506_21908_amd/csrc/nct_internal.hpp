@@ -1,0 +1,123 @@
+// Internal interfaces between the host engine (nct_api.cpp) and the kernel
+// launchers (nct_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace nct {
+
+template <typename R>
+struct cpx;
+
+// Projector tables on the device.  Sphere rows of all atoms are numbered
+// J = 0..Jtot-1; atom a owns rows [row_off[a], row_off[a] + ns[a]), sorted by
+// flat grid index, so the rows of one x-plane form a contiguous range.
+struct ProjTables {
+  int natoms = 0;
+  int P = 0;            // projectors per atom
+  int PP = 0;           // P padded to a multiple of 16
+  int Jtot = 0;         // total sphere rows
+  int max_kchunks = 0;  // max over atoms of ceil(2 ns / KC)
+  int max_rowtiles = 0; // max over atoms of ceil(2 ns / 16)
+  const int* row_off = nullptr;   // [natoms+1]
+  const int* pidx = nullptr;      // [Jtot] in-plane index y*NZ + z
+  const int* pr_off = nullptr;    // [NX+1] plane -> range list
+  const int* pr_begin = nullptr;  // [nranges]
+  const int* pr_end = nullptr;    // [nranges]
+  const void* beta = nullptr;     // complex R [Jtot][2][PP]
+  const double* energy = nullptr; // [natoms][PP] (0 beyond P)
+};
+
+template <typename R>
+struct StageArgs {
+  const void* tmp_in = nullptr;   // kinetic-applied mixed representation of w_in
+  void* tmp_out = nullptr;        // 2D (y,z) transform of w_out, or null
+  const void* w_in = nullptr;     // real-space input of this H application
+  const void* x_base = nullptr;   // Taylor base x (null: alpha ignored)
+  void* w_out = nullptr;          // alpha x + c H w_in
+  const R* fields = nullptr;      // [4][N] {v, b_x, b_y, b_z}
+  R bext[3] = {0, 0, 0};          // mu_B B_ext added to b
+  R cre = 1, cim = 0;             // coefficient c of H w
+  R alpha = 0;                    // coefficient of x_base
+  const void* Y = nullptr;        // nonlocal scatter rows [S][2][Jtot], or null
+  void* W = nullptr;              // output sphere rows [S][2][Jtot] of w_out, or null
+  // adjoint extras: acc += w_out (if acc != null)
+  void* acc = nullptr;
+};
+
+// Launchers (return hipError_t of the launch).  n = {NX, NY, NZ}.
+template <typename R>
+hipError_t launch_plane_stage(const int n[3], int S, const StageArgs<R>& a, const ProjTables& pt,
+                              const void* twy, const void* twz, hipStream_t st);
+// Forward 2D transform of B planes-sets (batch entries, each [NX][NY][NZ]); optionally gathers
+// sphere rows of the input into W (batch must then be 2S in state/spinor order).
+template <typename R>
+hipError_t launch_plane_fwd(const int n[3], int B, const void* in, void* out, void* W,
+                            const ProjTables* pt, const void* twy, const void* twz, hipStream_t st);
+// Inverse 2D transform; out = scale * result.
+template <typename R>
+hipError_t launch_plane_inv(const int n[3], int B, const void* in, void* out, R scale,
+                            const void* twy, const void* twz, hipStream_t st);
+// Column pass along x: dst = IDFT_x( mult * DFT_x(src) ), mult from per-axis |G|^2 tables.
+// mode 0: mult = kscale (g2x + g2yz); mode 1: mult = kscale / (g2x + g2yz), 0 at G = 0.
+template <typename R>
+hipError_t launch_xpass(const int n[3], int B, const void* src, void* dst, const R* g2x,
+                        const R* g2yz, R kscale, int mode, const void* twx, hipStream_t st);
+// Energy pass: per (batch, tile) partial sums of sum kscale*G^2 |X|^2 and sum |X|^2 of the full
+// 3D transform (input in the 2D-transformed form).  part: [B][ntiles][2] doubles.
+template <typename R>
+hipError_t launch_xpass_energy(const int n[3], int B, const void* src, const R* g2x,
+                               const R* g2yz, R kscale, const void* twx, double* part,
+                               int* ntiles_out, hipStream_t st);
+
+template <typename R>
+hipError_t launch_density(const void* psi, const double* occ, int S, size_t N, double* rho,
+                          hipStream_t st);
+
+// fields[4][N] = {v_ext + v_H + vbar, b_xc}; fields32 optional float copy;
+// part[nblk][8] = {N_e, M_x, M_y, M_z, E_loc, E_H, E_xc, 0} partial sums (not scaled by dV)
+hipError_t launch_fields(const double* rho, const double* vext, const double* vH, int xc,
+                         double thr, size_t N, double* fields, float* fields32, double* part,
+                         int* nblk_out, hipStream_t st);
+hipError_t launch_reduce_rows(const double* part, int nrows, int width, double* out,
+                              hipStream_t st);
+hipError_t launch_rho_to_n(const double* rho, size_t N, void* ncpx, hipStream_t st);
+hipError_t launch_cpx_real(const void* c, size_t N, double* out, hipStream_t st);
+hipError_t launch_add_bext(const double* fields, size_t N, const double b[3], double* out,
+                           hipStream_t st);
+hipError_t launch_to_float(const double* in, size_t n, float* out, hipStream_t st);
+
+// Projectors: C = dV beta^H W (per atom), EC = E * C; Y = beta EC.
+template <typename R>
+hipError_t launch_proj_contract(const ProjTables& pt, const void* W, int S, double dV,
+                                void* Cpart, void* C, void* EC, hipStream_t st);
+template <typename R>
+hipError_t launch_proj_scatter(const ProjTables& pt, const void* EC, int S, void* Y,
+                               hipStream_t st);
+
+// Observables of the current state: assembles one 13-double row.
+struct ObsInputs {
+  const double* field_tot;  // [8] reduced field partials
+  const double* epart;      // [2S][ntiles][2] energy-pass partials
+  int ntiles;
+  const void* C;            // [natoms][PP][S] complex R (already times dV)
+  const double* energy;     // [natoms][PP]
+  const double* occ;        // [S]
+  int S, natoms, PP, precision;
+  double dV, invN, t;
+  double muB_B[3];          // mu_B B_ext(t)
+};
+hipError_t launch_obs_row(const ObsInputs& in, double* row, hipStream_t st);
+
+template <typename R>
+hipError_t launch_seed(const void* psi, const double* occ, int S, size_t N, double w0, double w1,
+                       double w2, double scale, void* lam, hipStream_t st);
+template <typename R>
+hipError_t launch_axpby(void* y, const void* x, size_t count, R a_re, R a_im, R b,
+                        hipStream_t st);
+
+bool plane_pair_supported(int ny, int nz);
+bool line_supported(int n);
+
+}  // namespace nct

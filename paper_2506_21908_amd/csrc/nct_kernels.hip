@@ -1,0 +1,978 @@
+// HIP kernels of the non-collinear TDDFT step for gfx950 (MI355X), wave64.
+//
+// H application (Eq. HNC-SDFT / TDSDFT) as two passes over HBM:
+//   column pass  (k_xpass):  DFT_x -> multiply 1/2|G|^2/N -> IDFT_x on the
+//                            (y,z)-transformed states, tiles of TC columns in LDS;
+//   plane pass   (k_plane_stage): per (state, x-plane), both spinor components:
+//                            IDFT_yz -> T w; V w with the 2x2 local potential
+//                            [v + b.sigma]; + projector scatter rows; Taylor
+//                            (Horner) update out = alpha x + c H w; sphere rows of
+//                            out for the next projection; DFT_yz of out for the
+//                            next column pass.
+// Densities, exchange, Hartree and reductions are FP64.  The projector
+// contraction <beta|psi> and its scatter-back run on the matrix cores
+// (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "nct_fft.hpp"
+#include "nct_internal.hpp"
+
+namespace nct {
+
+// threads per plane workgroup: smallest power of two >= 64 with at most 9 points per thread
+__host__ __device__ constexpr int plane_nt(int np) {
+  int nt = 64;
+  while (nt < 1024 && (np + nt - 1) / nt > 9) nt *= 2;
+  return nt;
+}
+template <int NY, int NZ>
+constexpr size_t plane_lds_bytes(size_t elem) {
+  return (size_t(NY) * (NZ + 1) + NY + NZ) * elem;
+}
+
+// ---------------------------------------------------------------- block reductions
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  // wave64 butterfly then a fixed-order sum over waves: deterministic
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < NT / 64; ++k) s += red[k];
+  }
+  return s;  // valid on thread 0
+}
+
+// ---------------------------------------------------------------- plane pass: fused H stage
+template <typename R, int NY, int NZ>
+__global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a, ProjTables pt,
+                                                                   const cpx<R>* __restrict__ twy_g,
+                                                                   const cpx<R>* __restrict__ twz_g,
+                                                                   int S, int NX) {
+  constexpr int NP = NY * NZ;
+  constexpr int NT = plane_nt(NP);
+  constexpr int PZ = NZ + 1;
+  constexpr int PPT = (NP + NT - 1) / NT;
+  extern __shared__ double4 smem_d4[];
+  cpx<R>* plane = reinterpret_cast<cpx<R>*>(smem_d4);
+  cpx<R>* twy = plane + NY * PZ;
+  cpx<R>* twz = twy + NY;
+  const int tid = threadIdx.x;
+  const int L = xcd_logical(blockIdx.x, gridDim.x);
+  const int x = L / S;
+  const int i = L - x * S;
+  for (int k = tid; k < NY; k += NT) twy[k] = twy_g[k];
+  for (int k = tid; k < NZ; k += NT) twz[k] = twz_g[k];
+  const size_t N = size_t(NX) * NP;
+  size_t off[2];
+  off[0] = (size_t(2 * i) * NX + x) * NP;
+  off[1] = (size_t(2 * i + 1) * NX + x) * NP;
+  const cpx<R>* __restrict__ tin = reinterpret_cast<const cpx<R>*>(a.tmp_in);
+  cpx<R> hv[2][PPT];
+
+  // 1) kinetic part: inverse 2D transform of the column-pass output, both spinors
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int e = tid + j * NT;
+      if (e < NP) plane[(e / NZ) * PZ + (e % NZ)] = tin[off[s] + e];
+    }
+    __syncthreads();
+    plane_fft_inv<R, NY, NZ, PZ>(plane, twy, twz, tid, NT);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int e = tid + j * NT;
+      if (e < NP) hv[s][j] = plane[(e / NZ) * PZ + (e % NZ)];
+    }
+    __syncthreads();
+  }
+
+  // 2) local 2x2 potential and Taylor update, pointwise
+  const cpx<R>* __restrict__ win = reinterpret_cast<const cpx<R>*>(a.w_in);
+  const cpx<R>* __restrict__ xb = reinterpret_cast<const cpx<R>*>(a.x_base);
+  const R* __restrict__ F = a.fields;
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int e = tid + j * NT;
+    if (e < NP) {
+      const size_t p = size_t(x) * NP + e;
+      const R v = F[p];
+      const R bx = F[N + p] + a.bext[0];
+      const R by = F[2 * N + p] + a.bext[1];
+      const R bz = F[3 * N + p] + a.bext[2];
+      const cpx<R> wu = win[off[0] + e];
+      const cpx<R> wd = win[off[1] + e];
+      // up' = (v+bz) up + (bx - i by) dn ; dn' = (bx + i by) up + (v - bz) dn
+      cpx<R> hu, hd;
+      hu.x = hv[0][j].x + (v + bz) * wu.x + bx * wd.x + by * wd.y;
+      hu.y = hv[0][j].y + (v + bz) * wu.y + bx * wd.y - by * wd.x;
+      hd.x = hv[1][j].x + bx * wu.x - by * wu.y + (v - bz) * wd.x;
+      hd.y = hv[1][j].y + bx * wu.y + by * wu.x + (v - bz) * wd.y;
+      cpx<R> ou = {a.cre * hu.x - a.cim * hu.y, a.cre * hu.y + a.cim * hu.x};
+      cpx<R> od = {a.cre * hd.x - a.cim * hd.y, a.cre * hd.y + a.cim * hd.x};
+      if (xb) {
+        const cpx<R> xu = xb[off[0] + e];
+        const cpx<R> xd = xb[off[1] + e];
+        ou.x += a.alpha * xu.x;
+        ou.y += a.alpha * xu.y;
+        od.x += a.alpha * xd.x;
+        od.y += a.alpha * xd.y;
+      }
+      hv[0][j] = ou;
+      hv[1][j] = od;
+    }
+  }
+
+  // 3) per spinor: projector rows, outputs, forward 2D transform
+  const cpx<R>* __restrict__ Y = reinterpret_cast<const cpx<R>*>(a.Y);
+  cpx<R>* __restrict__ Wr = reinterpret_cast<cpx<R>*>(a.W);
+  cpx<R>* __restrict__ wout = reinterpret_cast<cpx<R>*>(a.w_out);
+  cpx<R>* __restrict__ acc = reinterpret_cast<cpx<R>*>(a.acc);
+  cpx<R>* __restrict__ tout = reinterpret_cast<cpx<R>*>(a.tmp_out);
+  const int r0 = pt.pr_off ? pt.pr_off[x] : 0;
+  const int r1 = pt.pr_off ? pt.pr_off[x + 1] : 0;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int e = tid + j * NT;
+      if (e < NP) plane[(e / NZ) * PZ + (e % NZ)] = hv[s][j];
+    }
+    __syncthreads();
+    const size_t rowbase = size_t(2 * i + s) * pt.Jtot;
+    if (Y) {
+      for (int r = r0; r < r1; ++r) {
+        const int jb = pt.pr_begin[r], je = pt.pr_end[r];
+        for (int J = jb + tid; J < je; J += NT) {
+          const int e = pt.pidx[J];
+          const cpx<R> y = Y[rowbase + J];
+          cpx<R>& d = plane[(e / NZ) * PZ + (e % NZ)];
+          d.x += a.cre * y.x - a.cim * y.y;
+          d.y += a.cre * y.y + a.cim * y.x;
+        }
+        __syncthreads();
+      }
+    }
+    if (Wr) {
+      for (int r = r0; r < r1; ++r) {
+        const int jb = pt.pr_begin[r], je = pt.pr_end[r];
+        for (int J = jb + tid; J < je; J += NT) {
+          const int e = pt.pidx[J];
+          Wr[rowbase + J] = plane[(e / NZ) * PZ + (e % NZ)];
+        }
+      }
+    }
+    if (wout || acc) {
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const int e = tid + j * NT;
+        if (e < NP) {
+          const cpx<R> o = plane[(e / NZ) * PZ + (e % NZ)];
+          if (wout) wout[off[s] + e] = o;
+          if (acc) {
+            cpx<R> q = acc[off[s] + e];
+            acc[off[s] + e] = q + o;
+          }
+        }
+      }
+    }
+    if (tout) {
+      __syncthreads();
+      plane_fft_fwd<R, NY, NZ, PZ>(plane, twy, twz, tid, NT);
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const int e = tid + j * NT;
+        if (e < NP) tout[off[s] + e] = plane[(e / NZ) * PZ + (e % NZ)];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- plane pass: transform only
+template <typename R, int NY, int NZ>
+__global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_fwd(const cpx<R>* in, cpx<R>* out,
+                                                                 cpx<R>* W, ProjTables pt,
+                                                                 const cpx<R>* __restrict__ twy_g,
+                                                                 const cpx<R>* __restrict__ twz_g,
+                                                                 int B, int NX) {
+  constexpr int NP = NY * NZ;
+  constexpr int NT = plane_nt(NP);
+  constexpr int PZ = NZ + 1;
+  extern __shared__ double4 smem_d4[];
+  cpx<R>* plane = reinterpret_cast<cpx<R>*>(smem_d4);
+  cpx<R>* twy = plane + NY * PZ;
+  cpx<R>* twz = twy + NY;
+  const int tid = threadIdx.x;
+  const int L = xcd_logical(blockIdx.x, gridDim.x);
+  const int x = L / B;
+  const int b = L - x * B;
+  for (int k = tid; k < NY; k += NT) twy[k] = twy_g[k];
+  for (int k = tid; k < NZ; k += NT) twz[k] = twz_g[k];
+  const size_t off = (size_t(b) * NX + x) * NP;
+  for (int e = tid; e < NP; e += NT) plane[(e / NZ) * PZ + (e % NZ)] = in[off + e];
+  __syncthreads();
+  if (W && pt.pr_off) {
+    const size_t rowbase = size_t(b) * pt.Jtot;
+    for (int r = pt.pr_off[x]; r < pt.pr_off[x + 1]; ++r) {
+      for (int J = pt.pr_begin[r] + tid; J < pt.pr_end[r]; J += NT) {
+        const int e = pt.pidx[J];
+        W[rowbase + J] = plane[(e / NZ) * PZ + (e % NZ)];
+      }
+    }
+    __syncthreads();
+  }
+  plane_fft_fwd<R, NY, NZ, PZ>(plane, twy, twz, tid, NT);
+  for (int e = tid; e < NP; e += NT) out[off + e] = plane[(e / NZ) * PZ + (e % NZ)];
+}
+
+template <typename R, int NY, int NZ>
+__global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_inv(const cpx<R>* in, cpx<R>* out,
+                                                                 R scale,
+                                                                 const cpx<R>* __restrict__ twy_g,
+                                                                 const cpx<R>* __restrict__ twz_g,
+                                                                 int B, int NX) {
+  constexpr int NP = NY * NZ;
+  constexpr int NT = plane_nt(NP);
+  constexpr int PZ = NZ + 1;
+  extern __shared__ double4 smem_d4[];
+  cpx<R>* plane = reinterpret_cast<cpx<R>*>(smem_d4);
+  cpx<R>* twy = plane + NY * PZ;
+  cpx<R>* twz = twy + NY;
+  const int tid = threadIdx.x;
+  const int L = xcd_logical(blockIdx.x, gridDim.x);
+  const int x = L / B;
+  const int b = L - x * B;
+  for (int k = tid; k < NY; k += NT) twy[k] = twy_g[k];
+  for (int k = tid; k < NZ; k += NT) twz[k] = twz_g[k];
+  const size_t off = (size_t(b) * NX + x) * NP;
+  for (int e = tid; e < NP; e += NT) plane[(e / NZ) * PZ + (e % NZ)] = in[off + e];
+  __syncthreads();
+  plane_fft_inv<R, NY, NZ, PZ>(plane, twy, twz, tid, NT);
+  for (int e = tid; e < NP; e += NT) out[off + e] = cscale(plane[(e / NZ) * PZ + (e % NZ)], scale);
+}
+
+// ---------------------------------------------------------------- column pass along x
+template <typename R>
+constexpr int xpass_tc(int nx) {
+  // widest tile (64, 32, 16 columns) whose LDS footprint stays within 32 KiB
+  const int b = int(sizeof(R)) * 2;
+  if (nx * 64 * b <= 32768) return 64;
+  if (nx * 32 * b <= 32768) return 32;
+  return 16;
+}
+constexpr int XP_NT = 256;
+
+template <typename R, int NX, int TC>
+__global__ __launch_bounds__(XP_NT) void k_xpass(const cpx<R>* src, cpx<R>* dst, int NYZ,
+                                                 const R* __restrict__ g2x,
+                                                 const R* __restrict__ g2yz, R kscale, int mode,
+                                                 const cpx<R>* __restrict__ twx_g) {
+  __shared__ cpx<R> tile[NX * TC];
+  __shared__ cpx<R> tw[NX];
+  const int tid = threadIdx.x;
+  const int tiles = NYZ / TC;
+  const int b = blockIdx.x / tiles;
+  const int tl = blockIdx.x - b * tiles;
+  const int q0 = tl * TC;
+  for (int k = tid; k < NX; k += XP_NT) tw[k] = twx_g[k];
+  const size_t base = size_t(b) * NX * NYZ + q0;
+  for (int e = tid; e < NX * TC; e += XP_NT) {
+    const int xx = e / TC, c = e - (e / TC) * TC;
+    tile[e] = src[base + size_t(xx) * NYZ + c];
+  }
+  __syncthreads();
+  lds_fft<R, NX, TC, 1, TC, true>(tile, tw, tid, XP_NT);
+  for (int e = tid; e < NX * TC; e += XP_NT) {
+    const int xx = e / TC, c = e - (e / TC) * TC;
+    const R g = g2x[xx] + g2yz[q0 + c];
+    R m;
+    if (mode == 0) m = kscale * g;
+    else m = g > R(0) ? kscale / g : R(0);
+    tile[e] = cscale(tile[e], m);
+  }
+  __syncthreads();
+  lds_fft<R, NX, TC, 1, TC, false>(tile, tw, tid, XP_NT);
+  for (int e = tid; e < NX * TC; e += XP_NT) {
+    const int xx = e / TC, c = e - (e / TC) * TC;
+    dst[base + size_t(xx) * NYZ + c] = tile[e];
+  }
+}
+
+template <typename R, int NX, int TC>
+__global__ __launch_bounds__(XP_NT) void k_xpass_energy(const cpx<R>* src, int NYZ,
+                                                        const R* __restrict__ g2x,
+                                                        const R* __restrict__ g2yz, R kscale,
+                                                        const cpx<R>* __restrict__ twx_g,
+                                                        double* part) {
+  __shared__ cpx<R> tile[NX * TC];
+  __shared__ cpx<R> tw[NX];
+  __shared__ double red[XP_NT / 64];
+  const int tid = threadIdx.x;
+  const int tiles = NYZ / TC;
+  const int b = blockIdx.x / tiles;
+  const int tl = blockIdx.x - b * tiles;
+  const int q0 = tl * TC;
+  for (int k = tid; k < NX; k += XP_NT) tw[k] = twx_g[k];
+  const size_t base = size_t(b) * NX * NYZ + q0;
+  for (int e = tid; e < NX * TC; e += XP_NT) {
+    const int xx = e / TC, c = e - (e / TC) * TC;
+    tile[e] = src[base + size_t(xx) * NYZ + c];
+  }
+  __syncthreads();
+  lds_fft<R, NX, TC, 1, TC, true>(tile, tw, tid, XP_NT);
+  double s1 = 0.0, s2 = 0.0;
+  for (int e = tid; e < NX * TC; e += XP_NT) {
+    const int xx = e / TC, c = e - (e / TC) * TC;
+    const double g = double(g2x[xx]) + double(g2yz[q0 + c]);
+    const double a2 = double(tile[e].x) * double(tile[e].x) + double(tile[e].y) * double(tile[e].y);
+    s1 += double(kscale) * g * a2;
+    s2 += a2;
+  }
+  const double t1 = block_sum<XP_NT>(s1, red);
+  const double t2 = block_sum<XP_NT>(s2, red);
+  if (tid == 0) {
+    part[size_t(blockIdx.x) * 2 + 0] = t1;
+    part[size_t(blockIdx.x) * 2 + 1] = t2;
+  }
+}
+
+// ---------------------------------------------------------------- density (Eq. density4)
+template <typename R>
+__global__ __launch_bounds__(256) void k_density(const cpx<R>* __restrict__ psi,
+                                                 const double* __restrict__ occ, int S, size_t N,
+                                                 double* __restrict__ rho) {
+  const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p >= N) return;
+  double uu = 0, dd = 0, udr = 0, udi = 0;
+#pragma unroll 4
+  for (int i = 0; i < S; ++i) {
+    const double f = occ[i];
+    const cpx<R> u = psi[size_t(2 * i) * N + p];
+    const cpx<R> d = psi[size_t(2 * i + 1) * N + p];
+    const double ux = u.x, uy = u.y, dx = d.x, dy = d.y;
+    uu += f * (ux * ux + uy * uy);
+    dd += f * (dx * dx + dy * dy);
+    udr += f * (ux * dx + uy * dy);   // Re(u d*)
+    udi += f * (uy * dx - ux * dy);   // Im(u d*)
+  }
+  rho[p] = uu;
+  rho[N + p] = dd;
+  rho[2 * N + p] = udr;
+  rho[3 * N + p] = udi;
+}
+
+// ---------------------------------------------------------------- exchange + fields (FP64)
+// Locally collinear Slater exchange (Eqs. LC+ALDA2, LC+ALDA):
+//   n_s = (n +/- |m|)/2, v_s = -(6/pi)^(1/3) n_s^(1/3), vbar = (v_up+v_dn)/2,
+//   b_xc = (v_up - v_dn)/2 m/|m| (0 below threshold), e_x = -(3/4)(6/pi)^(1/3) sum n_s^(4/3).
+// v_up - v_dn is evaluated as -(6/pi)^(1/3) (n_up - n_dn) / (n_up^(2/3) + (n_up n_dn)^(1/3) + n_dn^(2/3)).
+__global__ __launch_bounds__(256) void k_fields(const double* __restrict__ rho,
+                                                const double* __restrict__ vext,
+                                                const double* __restrict__ vH, int xc, double thr,
+                                                size_t N, double* __restrict__ fields,
+                                                float* __restrict__ f32, double* __restrict__ part) {
+  __shared__ double red[4];
+  const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
+  double n = 0, mx = 0, my = 0, mz = 0, eloc = 0, eh = 0, ex = 0;
+  if (p < N) {
+    const double ruu = rho[p], rdd = rho[N + p], rr = rho[2 * N + p], ri = rho[3 * N + p];
+    n = ruu + rdd;
+    mx = 2.0 * rr;
+    my = -2.0 * ri;
+    mz = ruu - rdd;
+    const double ve = vext ? vext[p] : 0.0;
+    const double vh = vH ? vH[p] : 0.0;
+    double vbar = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
+    if (xc) {
+      const double c = 1.2407009817988000;  // (6/pi)^(1/3)
+      const double mu = sqrt(mx * mx + my * my + mz * mz);
+      const double nu = fmax(0.5 * (n + mu), 0.0);
+      const double nd = fmax(0.5 * (n - mu), 0.0);
+      const double cu = cbrt(nu), cd = cbrt(nd);
+      vbar = -0.5 * c * (cu + cd);
+      ex = -0.75 * c * (nu * cu + nd * cd);
+      if (mu >= thr) {
+        const double den = cu * cu + cu * cd + cd * cd;
+        const double bmag = den > 0.0 ? -0.5 * c * (nu - nd) / den : 0.0;
+        const double s = bmag / mu;
+        bx = s * mx;
+        by = s * my;
+        bz = s * mz;
+      }
+    }
+    const double v = ve + vh + vbar;
+    fields[p] = v;
+    fields[N + p] = bx;
+    fields[2 * N + p] = by;
+    fields[3 * N + p] = bz;
+    if (f32) {
+      f32[p] = float(v);
+      f32[N + p] = float(bx);
+      f32[2 * N + p] = float(by);
+      f32[3 * N + p] = float(bz);
+    }
+    eloc = ve * n;
+    eh = 0.5 * vh * n;
+  }
+  const double vals[7] = {n, mx, my, mz, eloc, eh, ex};
+#pragma unroll
+  for (int k = 0; k < 7; ++k) {
+    const double t = block_sum<256>(vals[k], red);
+    if (threadIdx.x == 0) part[size_t(blockIdx.x) * 8 + k] = t;
+  }
+  if (threadIdx.x == 0) part[size_t(blockIdx.x) * 8 + 7] = 0.0;
+}
+
+// out[w] = sum_r part[r*width + w], fixed order
+__global__ __launch_bounds__(256) void k_reduce_rows(const double* __restrict__ part, int nrows,
+                                                     int width, double* __restrict__ out) {
+  __shared__ double red[4];
+  for (int w = 0; w < width; ++w) {
+    double s = 0.0;
+    for (int r = threadIdx.x; r < nrows; r += 256) s += part[size_t(r) * width + w];
+    const double t = block_sum<256>(s, red);
+    if (threadIdx.x == 0) out[w] = t;
+  }
+}
+
+__global__ void k_rho_to_n(const double* __restrict__ rho, size_t N, cpx<double>* __restrict__ out) {
+  const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p < N) out[p] = {rho[p] + rho[N + p], 0.0};
+}
+__global__ void k_cpx_real(const cpx<double>* __restrict__ c, size_t N, double* __restrict__ out) {
+  const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p < N) out[p] = c[p].x;
+}
+__global__ void k_add_bext(const double* __restrict__ f, size_t N, double b0, double b1, double b2,
+                           double* __restrict__ out) {
+  const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p < N) {
+    out[p] = f[p];
+    out[N + p] = f[N + p] + b0;
+    out[2 * N + p] = f[2 * N + p] + b1;
+    out[3 * N + p] = f[3 * N + p] + b2;
+  }
+}
+__global__ void k_to_float(const double* __restrict__ in, size_t n, float* __restrict__ out) {
+  const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p < n) out[p] = float(in[p]);
+}
+
+// ---------------------------------------------------------------- projectors on the matrix cores
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct mfma16;
+// Output element r of lane l is D[row(r, l/16)][l%16]: the f64 instruction interleaves the
+// four row groups across registers, the f32 one keeps four consecutive rows per lane.
+template <>
+struct mfma16<double> {
+  typedef d4v acc;
+  static __device__ __forceinline__ int row(int r, int kl) { return 4 * r + kl; }
+  static __device__ __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ acc op(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct mfma16<float> {
+  typedef f4v acc;
+  static __device__ __forceinline__ int row(int r, int kl) { return 4 * kl + r; }
+  static __device__ __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ acc op(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr int KC = 64;  // contraction K chunk per wave
+
+// Cpart[a][kc][p][i] = sum_{k in chunk} conj(beta[a][k][p]) W[i][k], k = 2 (J - off_a) + s.
+// One wave: two 16x16 output tiles (p < 32) of 16 states; A/B operands as
+// A[row = lane%16][k = lane/16], B[k = lane/16][col = lane%16]; D rows from mfma16::row.
+template <typename R>
+__global__ __launch_bounds__(64) void k_proj_contract(ProjTables pt, const cpx<R>* __restrict__ W,
+                                                      int S, cpx<double>* __restrict__ Cpart) {
+  using M = mfma16<R>;
+  const int a = blockIdx.x, nt = blockIdx.y, kc = blockIdx.z;
+  const int off = pt.row_off[a];
+  const int K = 2 * (pt.row_off[a + 1] - off);
+  if (kc * KC >= K) return;
+  const int lane = threadIdx.x;
+  const int col = lane & 15, kl = lane >> 4;
+  const int i = nt * 16 + col;
+  const cpx<R>* __restrict__ beta = reinterpret_cast<const cpx<R>*>(pt.beta);
+  const int nmt = pt.PP / 16;
+  typename M::acc ar[2], ai[2];
+  ar[0] = M::zero(); ar[1] = M::zero(); ai[0] = M::zero(); ai[1] = M::zero();
+  const int kend = min(K, kc * KC + KC);
+  for (int k0 = kc * KC; k0 < kend; k0 += 4) {
+    const int k = k0 + kl;
+    R br = 0, bi = 0;
+    if (k < K && i < S) {
+      const int J = off + (k >> 1), s = k & 1;
+      const cpx<R> w = W[size_t(2 * i + s) * pt.Jtot + J];
+      br = w.x;
+      bi = w.y;
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      if (mt < nmt) {
+        const int p = mt * 16 + col;
+        R xr = 0, xi = 0;
+        if (k < K) {
+          const cpx<R> bb = beta[(size_t(2 * off) + k) * pt.PP + p];
+          xr = bb.x;
+          xi = bb.y;
+        }
+        ar[mt] = M::op(xr, br, ar[mt]);
+        ar[mt] = M::op(xi, bi, ar[mt]);
+        ai[mt] = M::op(xr, bi, ai[mt]);
+        ai[mt] = M::op(-xi, br, ai[mt]);
+      }
+    }
+  }
+  const int nch = pt.max_kchunks;
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    if (mt >= nmt) break;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int p = mt * 16 + M::row(r, kl);
+      if (i < S)
+        Cpart[((size_t(a) * nch + kc) * pt.PP + p) * S + i] = {double(ar[mt][r]), double(ai[mt][r])};
+    }
+  }
+}
+
+// C[a][p][i] = dV sum_kc Cpart; EC = E[a][p] C (R precision)
+template <typename R>
+__global__ __launch_bounds__(256) void k_proj_reduce(ProjTables pt, const cpx<double>* __restrict__ Cpart,
+                                                     int S, double dV, cpx<double>* __restrict__ C,
+                                                     cpx<R>* __restrict__ EC) {
+  const size_t idx = size_t(blockIdx.x) * 256 + threadIdx.x;
+  const size_t total = size_t(pt.natoms) * pt.PP * S;
+  if (idx >= total) return;
+  const int i = int(idx % S);
+  const int p = int((idx / S) % pt.PP);
+  const int a = int(idx / (size_t(S) * pt.PP));
+  const int K = 2 * (pt.row_off[a + 1] - pt.row_off[a]);
+  const int nch_a = (K + KC - 1) / KC;
+  double sr = 0, si = 0;
+  for (int kc = 0; kc < nch_a; ++kc) {
+    const cpx<double> v = Cpart[((size_t(a) * pt.max_kchunks + kc) * pt.PP + p) * S + i];
+    sr += v.x;
+    si += v.y;
+  }
+  sr *= dV;
+  si *= dV;
+  C[idx] = {sr, si};
+  const double e = pt.energy[size_t(a) * pt.PP + p];
+  EC[idx] = {R(e * sr), R(e * si)};
+}
+
+// Y[i][s][J] = sum_p beta[J][s][p] EC[a][p][i]; rows k = 2 (J - off_a) + s
+template <typename R>
+__global__ __launch_bounds__(64) void k_proj_scatter(ProjTables pt, const cpx<R>* __restrict__ EC,
+                                                     int S, cpx<R>* __restrict__ Y) {
+  using M = mfma16<R>;
+  const int a = blockIdx.x, rt = blockIdx.y, nt = blockIdx.z;
+  const int off = pt.row_off[a];
+  const int K2 = 2 * (pt.row_off[a + 1] - off);
+  if (rt * 16 >= K2) return;
+  const int lane = threadIdx.x;
+  const int col = lane & 15, kl = lane >> 4;
+  const int row = rt * 16 + col;
+  const int i = nt * 16 + col;
+  const cpx<R>* __restrict__ beta = reinterpret_cast<const cpx<R>*>(pt.beta);
+  typename M::acc yr = M::zero(), yi = M::zero();
+  for (int k0 = 0; k0 < pt.PP; k0 += 4) {
+    const int p = k0 + kl;
+    R xr = 0, xi = 0, er = 0, ei = 0;
+    if (row < K2) {
+      const cpx<R> bb = beta[(size_t(2 * off) + row) * pt.PP + p];
+      xr = bb.x;
+      xi = bb.y;
+    }
+    if (i < S) {
+      const cpx<R> ec = EC[(size_t(a) * pt.PP + p) * S + i];
+      er = ec.x;
+      ei = ec.y;
+    }
+    yr = M::op(xr, er, yr);
+    yr = M::op(-xi, ei, yr);
+    yi = M::op(xr, ei, yi);
+    yi = M::op(xi, er, yi);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int rr = rt * 16 + M::row(r, kl);
+    if (rr < K2 && i < S) {
+      const int J = off + (rr >> 1), s = rr & 1;
+      Y[size_t(2 * i + s) * pt.Jtot + J] = {yr[r], yi[r]};
+    }
+  }
+}
+
+// ---------------------------------------------------------------- observables row
+__global__ __launch_bounds__(256) void k_obs_row(ObsInputs in, double* __restrict__ row) {
+  __shared__ double red[4];
+  __shared__ double maxerr[256];
+  const int tid = threadIdx.x;
+  double ekin = 0.0, mx = 0.0, enl = 0.0;
+  for (int i = tid; i < in.S; i += 256) {
+    double e = 0.0, nn = 0.0;
+    for (int s = 0; s < 2; ++s) {
+      for (int t = 0; t < in.ntiles; ++t) {
+        const double* q = in.epart + (size_t(2 * i + s) * in.ntiles + t) * 2;
+        e += q[0];
+        nn += q[1];
+      }
+    }
+    ekin += in.occ[i] * e * in.dV;
+    mx = fmax(mx, fabs(nn * in.invN * in.dV - 1.0));
+  }
+  if (in.C) {
+    const size_t total = size_t(in.natoms) * in.PP * in.S;
+    const cpx<double>* C = reinterpret_cast<const cpx<double>*>(in.C);
+    for (size_t idx = tid; idx < total; idx += 256) {
+      const int i = int(idx % in.S);
+      const int p = int((idx / in.S) % in.PP);
+      const int a = int(idx / (size_t(in.S) * in.PP));
+      const cpx<double> c = C[idx];
+      enl += in.occ[i] * in.energy[size_t(a) * in.PP + p] * (c.x * c.x + c.y * c.y);
+    }
+  }
+  const double Ekin = block_sum<256>(ekin, red);
+  const double Enl = block_sum<256>(enl, red);
+  maxerr[tid] = mx;
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int k = 0; k < 256; ++k) m = fmax(m, maxerr[k]);
+    const double* ft = in.field_tot;
+    const double dV = in.dV;
+    const double Ne = ft[0] * dV, Mx = ft[1] * dV, My = ft[2] * dV, Mz = ft[3] * dV;
+    const double Eloc = ft[4] * dV, EH = ft[5] * dV, Exc = ft[6] * dV;
+    const double EZ = in.muB_B[0] * Mx + in.muB_B[1] * My + in.muB_B[2] * Mz;
+    row[0] = in.t;
+    row[1] = Ne;
+    row[2] = Mx;
+    row[3] = My;
+    row[4] = Mz;
+    row[5] = Ekin + Eloc + Enl + EH + Exc + EZ;
+    row[6] = Ekin;
+    row[7] = Eloc;
+    row[8] = Enl;
+    row[9] = EH;
+    row[10] = Exc;
+    row[11] = EZ;
+    row[12] = m;
+  }
+}
+
+// ---------------------------------------------------------------- small pointwise kernels
+// lam_i = scale f_i (w . sigma) psi_i
+template <typename R>
+__global__ void k_seed(const cpx<R>* __restrict__ psi, const double* __restrict__ occ, int S,
+                       size_t N, double w0, double w1, double w2, double scale,
+                       cpx<R>* __restrict__ lam) {
+  const size_t idx = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= size_t(S) * N) return;
+  const int i = int(idx / N);
+  const size_t p = idx - size_t(i) * N;
+  const double f = scale * occ[i];
+  const cpx<R> u = psi[size_t(2 * i) * N + p];
+  const cpx<R> d = psi[size_t(2 * i + 1) * N + p];
+  // (w.sigma) (u, d) = (w2 u + (w0 - i w1) d, (w0 + i w1) u - w2 d)
+  const double ux = u.x, uy = u.y, dx = d.x, dy = d.y;
+  const double ox = w2 * ux + w0 * dx + w1 * dy;
+  const double oy = w2 * uy + w0 * dy - w1 * dx;
+  const double px = w0 * ux - w1 * uy - w2 * dx;
+  const double py = w0 * uy + w1 * ux - w2 * dy;
+  lam[size_t(2 * i) * N + p] = {R(f * ox), R(f * oy)};
+  lam[size_t(2 * i + 1) * N + p] = {R(f * px), R(f * py)};
+}
+
+// y = (a_re + i a_im) x + b y
+template <typename R>
+__global__ void k_axpby(cpx<R>* __restrict__ y, const cpx<R>* __restrict__ x, size_t count,
+                        R are, R aim, R b) {
+  const size_t idx = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= count) return;
+  const cpx<R> xv = x[idx];
+  const cpx<R> yv = y[idx];
+  y[idx] = {are * xv.x - aim * xv.y + b * yv.x, are * xv.y + aim * xv.x + b * yv.y};
+}
+
+// ================================================================ launchers
+static inline unsigned nblocks(size_t n, unsigned bs) { return unsigned((n + bs - 1) / bs); }
+
+#define NCT_PLANE_PAIRS(X) \
+  X(8, 8) X(12, 12) X(16, 16) X(24, 24) X(32, 32) X(48, 48) X(64, 64) X(96, 96) \
+  X(8, 16) X(16, 8) X(12, 16) X(16, 12) X(16, 24) X(24, 16)
+#define NCT_LINES(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96)
+
+bool plane_pair_supported(int ny, int nz) {
+#define X(a, b) if (ny == a && nz == b) return true;
+  NCT_PLANE_PAIRS(X)
+#undef X
+  return false;
+}
+bool line_supported(int n) {
+#define X(a) if (n == a) return true;
+  NCT_LINES(X)
+#undef X
+  return false;
+}
+
+template <typename K>
+static hipError_t set_lds(K kern, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+
+template <typename R>
+hipError_t launch_plane_stage(const int n[3], int S, const StageArgs<R>& a, const ProjTables& pt,
+                              const void* twy, const void* twz, hipStream_t st) {
+  const unsigned grid = unsigned(S) * unsigned(n[0]);
+#define X(A, B)                                                                             \
+  if (n[1] == A && n[2] == B) {                                                             \
+    constexpr size_t lds = plane_lds_bytes<A, B>(sizeof(cpx<R>));                           \
+    auto kern = k_plane_stage<R, A, B>;                                                     \
+    hipError_t e = set_lds(kern, lds);                                                      \
+    if (e != hipSuccess) return e;                                                          \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(plane_nt(A * B)), lds, st, a, pt,             \
+                       reinterpret_cast<const cpx<R>*>(twy), reinterpret_cast<const cpx<R>*>(twz), \
+                       S, n[0]);                                                            \
+    return hipGetLastError();                                                               \
+  }
+  NCT_PLANE_PAIRS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+template <typename R>
+hipError_t launch_plane_fwd(const int n[3], int B, const void* in, void* out, void* W,
+                            const ProjTables* pt, const void* twy, const void* twz, hipStream_t st) {
+  const unsigned grid = unsigned(B) * unsigned(n[0]);
+  ProjTables none;
+  const ProjTables& p = pt ? *pt : none;
+#define X(A, BB)                                                                            \
+  if (n[1] == A && n[2] == BB) {                                                            \
+    constexpr size_t lds = plane_lds_bytes<A, BB>(sizeof(cpx<R>));                          \
+    auto kern = k_plane_fwd<R, A, BB>;                                                      \
+    hipError_t e = set_lds(kern, lds);                                                      \
+    if (e != hipSuccess) return e;                                                          \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(plane_nt(A * BB)), lds, st,                   \
+                       reinterpret_cast<const cpx<R>*>(in), reinterpret_cast<cpx<R>*>(out),  \
+                       reinterpret_cast<cpx<R>*>(W), p,                                     \
+                       reinterpret_cast<const cpx<R>*>(twy), reinterpret_cast<const cpx<R>*>(twz), \
+                       B, n[0]);                                                            \
+    return hipGetLastError();                                                               \
+  }
+  NCT_PLANE_PAIRS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+template <typename R>
+hipError_t launch_plane_inv(const int n[3], int B, const void* in, void* out, R scale,
+                            const void* twy, const void* twz, hipStream_t st) {
+  const unsigned grid = unsigned(B) * unsigned(n[0]);
+#define X(A, BB)                                                                            \
+  if (n[1] == A && n[2] == BB) {                                                            \
+    constexpr size_t lds = plane_lds_bytes<A, BB>(sizeof(cpx<R>));                          \
+    auto kern = k_plane_inv<R, A, BB>;                                                      \
+    hipError_t e = set_lds(kern, lds);                                                      \
+    if (e != hipSuccess) return e;                                                          \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(plane_nt(A * BB)), lds, st,                   \
+                       reinterpret_cast<const cpx<R>*>(in), reinterpret_cast<cpx<R>*>(out),  \
+                       scale, reinterpret_cast<const cpx<R>*>(twy),                         \
+                       reinterpret_cast<const cpx<R>*>(twz), B, n[0]);                      \
+    return hipGetLastError();                                                               \
+  }
+  NCT_PLANE_PAIRS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+template <typename R>
+hipError_t launch_xpass(const int n[3], int B, const void* src, void* dst, const R* g2x,
+                        const R* g2yz, R kscale, int mode, const void* twx, hipStream_t st) {
+  const int NYZ = n[1] * n[2];
+#define X(A)                                                                                \
+  if (n[0] == A) {                                                                          \
+    constexpr int TCP = xpass_tc<R>(A);                                                     \
+    if (NYZ % TCP == 0) {                                                                   \
+      hipLaunchKernelGGL((k_xpass<R, A, TCP>), dim3(unsigned(B) * unsigned(NYZ / TCP)),      \
+                         dim3(XP_NT), 0, st, reinterpret_cast<const cpx<R>*>(src),           \
+                         reinterpret_cast<cpx<R>*>(dst), NYZ, g2x, g2yz, kscale, mode,       \
+                         reinterpret_cast<const cpx<R>*>(twx));                              \
+    } else {                                                                                \
+      hipLaunchKernelGGL((k_xpass<R, A, 16>), dim3(unsigned(B) * unsigned(NYZ / 16)),        \
+                         dim3(XP_NT), 0, st, reinterpret_cast<const cpx<R>*>(src),           \
+                         reinterpret_cast<cpx<R>*>(dst), NYZ, g2x, g2yz, kscale, mode,       \
+                         reinterpret_cast<const cpx<R>*>(twx));                              \
+    }                                                                                       \
+    return hipGetLastError();                                                               \
+  }
+  NCT_LINES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+template <typename R>
+hipError_t launch_xpass_energy(const int n[3], int B, const void* src, const R* g2x,
+                               const R* g2yz, R kscale, const void* twx, double* part,
+                               int* ntiles_out, hipStream_t st) {
+  const int NYZ = n[1] * n[2];
+#define X(A)                                                                                \
+  if (n[0] == A) {                                                                          \
+    constexpr int TCP = xpass_tc<R>(A);                                                     \
+    if (NYZ % TCP == 0) {                                                                   \
+      *ntiles_out = NYZ / TCP;                                                              \
+      hipLaunchKernelGGL((k_xpass_energy<R, A, TCP>), dim3(unsigned(B) * unsigned(NYZ / TCP)), \
+                         dim3(XP_NT), 0, st, reinterpret_cast<const cpx<R>*>(src), NYZ, g2x,  \
+                         g2yz, kscale, reinterpret_cast<const cpx<R>*>(twx), part);          \
+    } else {                                                                                \
+      *ntiles_out = NYZ / 16;                                                               \
+      hipLaunchKernelGGL((k_xpass_energy<R, A, 16>), dim3(unsigned(B) * unsigned(NYZ / 16)),  \
+                         dim3(XP_NT), 0, st, reinterpret_cast<const cpx<R>*>(src), NYZ, g2x,  \
+                         g2yz, kscale, reinterpret_cast<const cpx<R>*>(twx), part);          \
+    }                                                                                       \
+    return hipGetLastError();                                                               \
+  }
+  NCT_LINES(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+template <typename R>
+hipError_t launch_density(const void* psi, const double* occ, int S, size_t N, double* rho,
+                          hipStream_t st) {
+  hipLaunchKernelGGL((k_density<R>), dim3(nblocks(N, 256)), dim3(256), 0, st,
+                     reinterpret_cast<const cpx<R>*>(psi), occ, S, N, rho);
+  return hipGetLastError();
+}
+
+hipError_t launch_fields(const double* rho, const double* vext, const double* vH, int xc,
+                         double thr, size_t N, double* fields, float* fields32, double* part,
+                         int* nblk_out, hipStream_t st) {
+  const unsigned nb = nblocks(N, 256);
+  *nblk_out = int(nb);
+  hipLaunchKernelGGL(k_fields, dim3(nb), dim3(256), 0, st, rho, vext, vH, xc, thr, N, fields,
+                     fields32, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_rows(const double* part, int nrows, int width, double* out,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(256), 0, st, part, nrows, width, out);
+  return hipGetLastError();
+}
+hipError_t launch_rho_to_n(const double* rho, size_t N, void* ncpx, hipStream_t st) {
+  hipLaunchKernelGGL(k_rho_to_n, dim3(nblocks(N, 256)), dim3(256), 0, st, rho, N,
+                     reinterpret_cast<cpx<double>*>(ncpx));
+  return hipGetLastError();
+}
+hipError_t launch_cpx_real(const void* c, size_t N, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_cpx_real, dim3(nblocks(N, 256)), dim3(256), 0, st,
+                     reinterpret_cast<const cpx<double>*>(c), N, out);
+  return hipGetLastError();
+}
+hipError_t launch_add_bext(const double* fields, size_t N, const double b[3], double* out,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_add_bext, dim3(nblocks(N, 256)), dim3(256), 0, st, fields, N, b[0], b[1],
+                     b[2], out);
+  return hipGetLastError();
+}
+hipError_t launch_to_float(const double* in, size_t n, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_float, dim3(nblocks(n, 256)), dim3(256), 0, st, in, n, out);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_proj_contract(const ProjTables& pt, const void* W, int S, double dV,
+                                void* Cpart, void* C, void* EC, hipStream_t st) {
+  if (pt.natoms == 0) return hipSuccess;
+  const unsigned ntile = unsigned((S + 15) / 16);
+  hipLaunchKernelGGL((k_proj_contract<R>), dim3(pt.natoms, ntile, pt.max_kchunks), dim3(64), 0, st,
+                     pt, reinterpret_cast<const cpx<R>*>(W), S,
+                     reinterpret_cast<cpx<double>*>(Cpart));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t total = size_t(pt.natoms) * pt.PP * S;
+  hipLaunchKernelGGL((k_proj_reduce<R>), dim3(nblocks(total, 256)), dim3(256), 0, st, pt,
+                     reinterpret_cast<const cpx<double>*>(Cpart), S, dV,
+                     reinterpret_cast<cpx<double>*>(C), reinterpret_cast<cpx<R>*>(EC));
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_proj_scatter(const ProjTables& pt, const void* EC, int S, void* Y,
+                               hipStream_t st) {
+  if (pt.natoms == 0) return hipSuccess;
+  const unsigned ntile = unsigned((S + 15) / 16);
+  hipLaunchKernelGGL((k_proj_scatter<R>), dim3(pt.natoms, pt.max_rowtiles, ntile), dim3(64), 0, st,
+                     pt, reinterpret_cast<const cpx<R>*>(EC), S, reinterpret_cast<cpx<R>*>(Y));
+  return hipGetLastError();
+}
+
+hipError_t launch_obs_row(const ObsInputs& in, double* row, hipStream_t st) {
+  hipLaunchKernelGGL(k_obs_row, dim3(1), dim3(256), 0, st, in, row);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_seed(const void* psi, const double* occ, int S, size_t N, double w0, double w1,
+                       double w2, double scale, void* lam, hipStream_t st) {
+  hipLaunchKernelGGL((k_seed<R>), dim3(nblocks(size_t(S) * N, 256)), dim3(256), 0, st,
+                     reinterpret_cast<const cpx<R>*>(psi), occ, S, N, w0, w1, w2, scale,
+                     reinterpret_cast<cpx<R>*>(lam));
+  return hipGetLastError();
+}
+template <typename R>
+hipError_t launch_axpby(void* y, const void* x, size_t count, R a_re, R a_im, R b,
+                        hipStream_t st) {
+  hipLaunchKernelGGL((k_axpby<R>), dim3(nblocks(count, 256)), dim3(256), 0, st,
+                     reinterpret_cast<cpx<R>*>(y), reinterpret_cast<const cpx<R>*>(x), count, a_re,
+                     a_im, b);
+  return hipGetLastError();
+}
+
+// explicit instantiations
+#define NCT_INST(R)                                                                                \
+  template hipError_t launch_plane_stage<R>(const int*, int, const StageArgs<R>&, const ProjTables&, \
+                                            const void*, const void*, hipStream_t);                \
+  template hipError_t launch_plane_fwd<R>(const int*, int, const void*, void*, void*,              \
+                                          const ProjTables*, const void*, const void*, hipStream_t); \
+  template hipError_t launch_plane_inv<R>(const int*, int, const void*, void*, R, const void*,     \
+                                          const void*, hipStream_t);                               \
+  template hipError_t launch_xpass<R>(const int*, int, const void*, void*, const R*, const R*, R,  \
+                                      int, const void*, hipStream_t);                              \
+  template hipError_t launch_xpass_energy<R>(const int*, int, const void*, const R*, const R*, R,  \
+                                             const void*, double*, int*, hipStream_t);             \
+  template hipError_t launch_density<R>(const void*, const double*, int, size_t, double*,          \
+                                        hipStream_t);                                              \
+  template hipError_t launch_proj_contract<R>(const ProjTables&, const void*, int, double, void*,  \
+                                              void*, void*, hipStream_t);                          \
+  template hipError_t launch_proj_scatter<R>(const ProjTables&, const void*, int, void*,           \
+                                             hipStream_t);                                         \
+  template hipError_t launch_seed<R>(const void*, const double*, int, size_t, double, double,      \
+                                     double, double, void*, hipStream_t);                          \
+  template hipError_t launch_axpby<R>(void*, const void*, size_t, R, R, R, hipStream_t);
+NCT_INST(double)
+NCT_INST(float)
+
+}  // namespace nct

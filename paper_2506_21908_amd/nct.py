@@ -1,0 +1,257 @@
+"""ctypes binding of libnct.so (include/nct.h): argument marshalling only.
+
+Every computation runs in the HIP library.  torch provides device memory and
+the stream.  If libnct.so is missing, or no GPU is present, the calls raise:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_void_p
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnct.so")
+
+NCT_OK, NCT_ERR_ARG, NCT_ERR_UNSUPPORTED, NCT_ERR_OOM, NCT_ERR_HIP, NCT_ERR_NONFINITE, NCT_ERR_STATE = range(7)
+NCT_FP64, NCT_FP32_MIXED = 0, 1
+STATUS_NAMES = {0: "NCT_OK", 1: "NCT_ERR_ARG", 2: "NCT_ERR_UNSUPPORTED", 3: "NCT_ERR_OOM",
+                4: "NCT_ERR_HIP", 5: "NCT_ERR_NONFINITE", 6: "NCT_ERR_STATE"}
+OBS_NAMES = ["t", "N_e", "M_x", "M_y", "M_z", "E_total", "E_kin", "E_loc", "E_NL", "E_H",
+             "E_xc", "E_Z", "max_norm_err"]
+
+
+class Channel(ctypes.Structure):
+    _fields_ = [("l", c_int), ("twoj", c_int), ("energy", c_double), ("rc", c_double)]
+
+
+class Pulse(ctypes.Structure):
+    _fields_ = [("A", c_double), ("omega", c_double), ("t0", c_double), ("tau", c_double),
+                ("phase", c_double), ("e1", c_double * 3), ("e2", c_double * 3)]
+
+
+class BField(ctypes.Structure):
+    _fields_ = [("B0", c_double * 3), ("npulses", c_int), ("pulses", POINTER(Pulse))]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n", c_int * 3), ("cell", c_double * 3), ("nstates", c_int),
+                ("occ", POINTER(c_double)), ("natoms", c_int), ("positions", POINTER(c_double)),
+                ("nchannels", c_int), ("channels", POINTER(Channel)), ("r_sphere", c_double),
+                ("xc", c_int), ("hartree", c_int), ("m_threshold", c_double), ("dt", c_double),
+                ("taylor_order", c_int), ("precision", c_int), ("tape_steps", c_int),
+                ("stream", c_void_p)]
+
+
+class NctError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_LIB = None
+
+
+def lib():
+    """Load libnct.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libnct.so not built at {LIB_PATH}; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.nct_create_system.argtypes = [POINTER(Params), POINTER(c_void_p)]
+        L.nct_create_system.restype = c_int
+        L.nct_destroy_system.argtypes = [c_void_p]
+        L.nct_destroy_system.restype = None
+        L.nct_last_error.argtypes = [c_void_p]
+        L.nct_last_error.restype = ctypes.c_char_p
+        L.nct_set_potentials.argtypes = [c_void_p, c_void_p, POINTER(BField), c_void_p]
+        L.nct_set_potentials.restype = c_int
+        L.nct_density_magnetization.argtypes = [c_void_p, c_void_p, c_double, c_void_p,
+                                                POINTER(c_double), c_int]
+        L.nct_density_magnetization.restype = c_int
+        L.nct_get_fields.argtypes = [c_void_p, c_double, c_void_p]
+        L.nct_get_fields.restype = c_int
+        L.nct_apply_hamiltonian.argtypes = [c_void_p, c_void_p, c_void_p, c_double]
+        L.nct_apply_hamiltonian.restype = c_int
+        L.nct_step.argtypes = [c_void_p, c_void_p, c_double, c_int, POINTER(c_double), c_int]
+        L.nct_step.restype = c_int
+        L.nct_magnetization_seed.argtypes = [c_void_p, c_void_p, POINTER(c_double), c_void_p]
+        L.nct_magnetization_seed.restype = c_int
+        L.nct_backward_step.argtypes = [c_void_p, c_int, c_void_p, c_double, c_void_p, c_void_p,
+                                        POINTER(c_double), POINTER(c_double)]
+        L.nct_backward_step.restype = c_int
+        L.nct_version.argtypes = []
+        L.nct_version.restype = ctypes.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def _dptr(x: np.ndarray):
+    return x.ctypes.data_as(POINTER(c_double))
+
+
+def _tptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+class System:
+    """One nct_system.  States are torch tensors [S, 2, nx, ny, nz] (complex128 or complex64)."""
+
+    def __init__(self, n: Sequence[int], cell: Sequence[float], nstates: int, occ=None,
+                 positions=None, channels=(), r_sphere: float = 2.5, xc: int = 1,
+                 hartree: int = 1, m_threshold: float = 1e-12, dt: float = 0.05,
+                 taylor_order: int = 4, precision: int = NCT_FP64, tape_steps: int = 0,
+                 stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("nct.System needs a GPU (no CPU fallback)")
+        L = lib()
+        self._keep = []
+        p = Params()
+        p.n = (c_int * 3)(*[int(v) for v in n])
+        p.cell = (c_double * 3)(*[float(v) for v in cell])
+        p.nstates = int(nstates)
+        if occ is not None:
+            occ = np.ascontiguousarray(occ, dtype=np.float64)
+            self._keep.append(occ)
+            p.occ = _dptr(occ)
+        pos = np.ascontiguousarray(np.zeros((0, 3)) if positions is None else positions,
+                                   dtype=np.float64).reshape(-1, 3)
+        self._keep.append(pos)
+        p.natoms = int(pos.shape[0])
+        p.positions = _dptr(pos) if pos.size else None
+        chans = (Channel * max(1, len(channels)))()
+        for k, c in enumerate(channels):
+            chans[k] = Channel(int(c.l), int(c.twoj), float(c.energy), float(c.rc))
+        self._keep.append(chans)
+        p.nchannels = len(channels)
+        p.channels = ctypes.cast(chans, POINTER(Channel)) if len(channels) else None
+        p.r_sphere = float(r_sphere)
+        p.xc, p.hartree = int(xc), int(hartree)
+        p.m_threshold = float(m_threshold)
+        p.dt = float(dt)
+        p.taylor_order = int(taylor_order)
+        p.precision = int(precision)
+        p.tape_steps = int(tape_steps)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        p.stream = c_void_p(stream.cuda_stream)
+        self.params = p
+        h = c_void_p()
+        rc = L.nct_create_system(ctypes.byref(p), ctypes.byref(h))
+        if rc != NCT_OK:
+            raise NctError(rc, L.nct_last_error(None).decode())
+        self.h = h
+        self.n = tuple(int(v) for v in n)
+        self.N = int(np.prod(self.n))
+        self.S = int(nstates)
+        self.precision = int(precision)
+        self.dtype = torch.complex128 if precision == NCT_FP64 else torch.complex64
+        self.npulses = 0
+
+    # ------------------------------------------------------------------ helpers
+    def _check(self, rc: int):
+        if rc != NCT_OK:
+            raise NctError(rc, lib().nct_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().nct_destroy_system(self.h)
+            self.h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def new_states(self):
+        import torch
+        return torch.empty((self.S, 2) + self.n, dtype=self.dtype, device="cuda")
+
+    # ------------------------------------------------------------------ C ABI
+    def set_potentials(self, v_ext=None, B0=None, pulses=None, fields=None):
+        bf = None
+        if B0 is not None or pulses is not None:
+            pl = list(pulses or [])
+            arr = (Pulse * max(1, len(pl)))()
+            for k, q in enumerate(pl):
+                arr[k] = Pulse(q.A, q.omega, q.t0, q.tau, getattr(q, "phase", 0.0),
+                               (c_double * 3)(*q.e1), (c_double * 3)(*q.e2))
+            bf = BField((c_double * 3)(*(B0 if B0 is not None else (0.0, 0.0, 0.0))), len(pl),
+                        ctypes.cast(arr, POINTER(Pulse)) if pl else None)
+            self._keep.append(arr)
+            self.npulses = len(pl)
+        self._check(lib().nct_set_potentials(self.h, _tptr(v_ext),
+                                             ctypes.byref(bf) if bf is not None else None,
+                                             _tptr(fields)))
+
+    def density_magnetization(self, psi, t: float = 0.0, rho_v=None, totals: bool = False,
+                              update_fields: bool = False):
+        tot = np.zeros(4)
+        self._check(lib().nct_density_magnetization(self.h, _tptr(psi), float(t), _tptr(rho_v),
+                                                     _dptr(tot) if totals else None,
+                                                     int(update_fields)))
+        return tot if totals else None
+
+    def get_fields(self, t: float, out):
+        self._check(lib().nct_get_fields(self.h, float(t), _tptr(out)))
+
+    def apply_hamiltonian(self, psi, hpsi, t: float = 0.0):
+        self._check(lib().nct_apply_hamiltonian(self.h, _tptr(psi), _tptr(hpsi), float(t)))
+
+    def step(self, psi, t0: float, nsteps: int, obs: bool = False, tape: bool = False):
+        out = np.zeros((max(nsteps, 1), 13)) if obs else None
+        self._check(lib().nct_step(self.h, _tptr(psi), float(t0), int(nsteps),
+                                   _dptr(out) if obs else None, int(tape)))
+        return out[:nsteps] if obs else None
+
+    def magnetization_seed(self, psi, w, lam):
+        wv = np.ascontiguousarray(w, dtype=np.float64)
+        self._check(lib().nct_magnetization_seed(self.h, _tptr(psi), _dptr(wv), _tptr(lam)))
+
+    def backward_step(self, tape_index: int, psi_n, t_n: float, lam_np1, lam_n, dLdtheta=None):
+        dLdB = np.zeros(6)
+        self._check(lib().nct_backward_step(self.h, int(tape_index), _tptr(psi_n), float(t_n),
+                                            _tptr(lam_np1), _tptr(lam_n), _dptr(dLdB),
+                                            _dptr(dLdtheta) if dLdtheta is not None else None))
+        return dLdB
+
+
+def system_from_workload(w, precision: int = NCT_FP64, tape_steps: int = 0, dt=None,
+                         taylor_order=None, stream=None) -> System:
+    """Create a System for a seeded workload and upload its v_ext and B field."""
+    import torch
+    s = System(w.n, w.L, w.nstates, occ=w.occ, positions=w.positions, channels=w.channels,
+               r_sphere=w.r_sphere, xc=w.xc, hartree=w.hartree, m_threshold=w.m_threshold,
+               dt=w.dt if dt is None else dt,
+               taylor_order=w.taylor_order if taylor_order is None else taylor_order,
+               precision=precision, tape_steps=tape_steps, stream=stream)
+    v = torch.from_numpy(np.ascontiguousarray(w.v_ext)).to("cuda")
+    s.set_potentials(v_ext=v, B0=w.bfield.B0, pulses=w.bfield.pulses)
+    torch.cuda.synchronize()
+    return s
+
+
+def states_to_device(psi0: np.ndarray, precision: int = NCT_FP64):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(psi0))
+    if precision == NCT_FP32_MIXED:
+        t = t.to(torch.complex64)
+    return t.to("cuda").contiguous()
+
+
+def version() -> str:
+    return lib().nct_version().decode()
