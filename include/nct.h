@@ -186,6 +186,29 @@ nct_status nct_backward_step(nct_system *sys, int tape_index, const void *psi_n_
                              const void *lam_np1_dev, void *lam_n_dev, double *dLdB_host,
                              double *dLdtheta_host);
 
+/* Kernel classes for the timing facility below. */
+enum {
+  NCT_K_PLANE_STAGE = 0,  /* fused plane pass of one H application / Taylor stage */
+  NCT_K_XPASS = 1,        /* column pass along x (kinetic multiplier) */
+  NCT_K_PLANE_FWD = 2,    /* forward yz transform of the input states */
+  NCT_K_DENSITY = 3,      /* spin density matrix reduction */
+  NCT_K_FIELDS = 4,       /* Poisson solve, exchange, field totals */
+  NCT_K_PROJ = 5,         /* projector contraction + scatter (MFMA) */
+  NCT_K_OBS = 6,          /* observables (energy pass, row assembly) */
+  NCT_K_ADJOINT = 7,      /* adjoint-only kernels (pair reductions, density back-propagation) */
+  NCT_K_COUNT = 8
+};
+
+/* Profiling aid.  nct_set_timing(sys, 1) resets the counters and starts recording a pair of
+ * HIP events around every kernel launch the system makes (on its stream); 0 stops.
+ * nct_get_timing synchronises the stream and returns for kernel class kclass the summed
+ * duration in milliseconds, the number of launches, and the algorithmic bytes and flops of
+ * those launches (compulsory HBM traffic and useful arithmetic of the launch's definition,
+ * not counters).  Outputs may be NULL. */
+nct_status nct_set_timing(nct_system *sys, int enable);
+nct_status nct_get_timing(nct_system *sys, int kclass, double *ms, long long *launches,
+                          double *bytes, double *flops);
+
 /* Library build string (architecture, precisions, grid sizes built). */
 const char *nct_version(void);
 

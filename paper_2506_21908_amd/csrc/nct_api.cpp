@@ -97,6 +97,20 @@ struct nct_system {
   void* C = nullptr;
   void* EC = nullptr;
   double* energy_dev = nullptr;
+
+  // kernel timing (profiling aid)
+  struct TimedLaunch {
+    int k;
+    hipEvent_t a, b;
+    double bytes, flops;
+  };
+  bool timing = false;
+  std::vector<TimedLaunch> pending;
+  std::vector<hipEvent_t> free_events;
+  double t_ms[NCT_K_COUNT] = {0};
+  long long t_count[NCT_K_COUNT] = {0};
+  double t_bytes[NCT_K_COUNT] = {0};
+  double t_flops[NCT_K_COUNT] = {0};
 };
 
 namespace {
@@ -141,6 +155,50 @@ nct_status upload(nct_system* s, const std::vector<T>& h, T** out) {
   if (!h.empty()) HIPCHK(s, hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
   *out = static_cast<T*>(p);
   return NCT_OK;
+}
+
+// ---------------------------------------------------------------- kernel timing
+hipEvent_t take_event(nct_system* s) {
+  if (!s->free_events.empty()) {
+    hipEvent_t e = s->free_events.back();
+    s->free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Runs launch(); when timing is on, brackets it with events and books bytes/flops on class k.
+template <typename F>
+hipError_t timed(nct_system* s, int k, double bytes, double flops, F&& launch) {
+  if (!s->timing) return launch();
+  hipEvent_t a = take_event(s), b = take_event(s);
+  if (!a || !b) return launch();
+  hipError_t e = hipEventRecord(a, s->st);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, s->st);
+  if (e != hipSuccess) return e;
+  s->pending.push_back({k, a, b, bytes, flops});
+  return hipSuccess;
+}
+
+// Call after the stream has been synchronised.
+void harvest_timing(nct_system* s) {
+  for (auto& t : s->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      s->t_ms[t.k] += ms;
+      s->t_count[t.k] += 1;
+      s->t_bytes[t.k] += t.bytes;
+      s->t_flops[t.k] += t.flops;
+    }
+    s->free_events.push_back(t.a);
+    s->free_events.push_back(t.b);
+  }
+  s->pending.clear();
 }
 
 // ---------------------------------------------------------------- FFT tables
@@ -417,6 +475,8 @@ struct Engine {
   const R* g2x() const { return sizeof(R) == 8 ? (const R*)s->g2x64 : (const R*)s->g2x32; }
   const R* g2yz() const { return sizeof(R) == 8 ? (const R*)s->g2yz64 : (const R*)s->g2yz32; }
   const R* fieldsR() const { return sizeof(R) == 8 ? (const R*)s->fields : (const R*)s->fields32; }
+  double psiB() const { return 2.0 * s->S * double(s->N) * sizeof(R) * 2; }
+  double rowsB() const { return 2.0 * s->S * double(s->pt.Jtot) * sizeof(R) * 2; }
 
   nct_status check(hipError_t e, const char* what) {
     if (e != hipSuccess) return fail(s, NCT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
@@ -427,39 +487,60 @@ struct Engine {
   nct_status fields_from_rho(bool store) {
     nct_status r;
     const double* vh = nullptr;
+    const double N = double(s->N);
+    const int K = NCT_K_FIELDS;
     if (s->prm.hartree) {
-      if ((r = check(launch_rho_to_n(s->rho, s->N, s->ncpx, s->st), "rho_to_n")) != NCT_OK) return r;
-      if ((r = check(launch_plane_fwd<double>(s->n, 1, s->ncpx, s->ncpx, nullptr, nullptr, s->tw64[1],
-                                              s->tw64[2], s->st), "poisson fwd")) != NCT_OK) return r;
-      if ((r = check(launch_xpass<double>(s->n, 1, s->ncpx, s->ncpx, s->g2x64, s->g2yz64,
-                                          4.0 * kPi / double(s->N), 1, s->tw64[0], s->st),
+      if ((r = check(timed(s, K, 32 * N, 0, [&] { return launch_rho_to_n(s->rho, s->N, s->ncpx, s->st); }),
+                     "rho_to_n")) != NCT_OK) return r;
+      if ((r = check(timed(s, K, 32 * N, 0, [&] {
+             return launch_plane_fwd<double>(s->n, 1, s->ncpx, s->ncpx, nullptr, nullptr, s->tw64[1],
+                                             s->tw64[2], s->st); }), "poisson fwd")) != NCT_OK) return r;
+      if ((r = check(timed(s, K, 32 * N, 0, [&] {
+             return launch_xpass<double>(s->n, 1, s->ncpx, s->ncpx, s->g2x64, s->g2yz64,
+                                         4.0 * kPi / double(s->N), 1, s->tw64[0], s->st); }),
                      "poisson x")) != NCT_OK) return r;
-      if ((r = check(launch_plane_inv<double>(s->n, 1, s->ncpx, s->ncpx, 1.0, s->tw64[1], s->tw64[2],
-                                              s->st), "poisson inv")) != NCT_OK) return r;
-      if ((r = check(launch_cpx_real(s->ncpx, s->N, s->vH, s->st), "cpx_real")) != NCT_OK) return r;
+      if ((r = check(timed(s, K, 32 * N, 0, [&] {
+             return launch_plane_inv<double>(s->n, 1, s->ncpx, s->ncpx, 1.0, s->tw64[1], s->tw64[2],
+                                             s->st); }), "poisson inv")) != NCT_OK) return r;
+      if ((r = check(timed(s, K, 24 * N, 0, [&] { return launch_cpx_real(s->ncpx, s->N, s->vH, s->st); }),
+                     "cpx_real")) != NCT_OK) return r;
       vh = s->vH;
     }
     int nb = 0;
     double* out = store ? s->fields : s->fields_scr;
     float* o32 = (store && !s->fp64) ? s->fields32 : nullptr;
-    if ((r = check(launch_fields(s->rho, s->vext, vh, s->prm.xc, s->prm.m_threshold, s->N, out, o32,
-                                 s->fpart, &nb, s->st), "fields")) != NCT_OK) return r;
-    if ((r = check(launch_reduce_rows(s->fpart, nb, 8, s->ftot, s->st), "reduce")) != NCT_OK) return r;
+    if ((r = check(timed(s, K, (32 + 16 + 32 + (o32 ? 16 : 0)) * N, 0, [&] {
+           return launch_fields(s->rho, s->vext, vh, s->prm.xc, s->prm.m_threshold, s->N, out, o32,
+                                s->fpart, &nb, s->st); }), "fields")) != NCT_OK) return r;
+    if ((r = check(timed(s, K, 64.0 * nb, 0, [&] { return launch_reduce_rows(s->fpart, nb, 8, s->ftot, s->st); }),
+                   "reduce")) != NCT_OK) return r;
     if (store) s->fields_valid = true;
     return NCT_OK;
   }
 
   nct_status density(const void* psi) {
-    return check(launch_density<R>(psi, s->occ, s->S, s->N, s->rho, s->st), "density");
+    return check(timed(s, NCT_K_DENSITY, psiB() + 32.0 * s->N, 0, [&] {
+                   return launch_density<R>(psi, s->occ, s->S, s->N, s->rho, s->st); }), "density");
+  }
+
+  double proj_flops() const { return 8.0 * s->pt.PP * 2.0 * s->pt.Jtot * s->S; }
+  double beta_bytes() const { return 2.0 * s->pt.Jtot * s->pt.PP * sizeof(R) * 2; }
+
+  nct_status contract(const void* W) {
+    const double cpB = double(s->natoms) * s->pt.PP * s->S * 16.0;
+    return check(timed(s, NCT_K_PROJ, rowsB() + beta_bytes() + cpB * s->pt.max_kchunks, proj_flops(), [&] {
+                   return launch_proj_contract<R>(s->pt, W, s->S, s->dV, s->Cpart, s->C, s->EC, s->st); }),
+                 "proj_contract");
   }
 
   // NL projections of the sphere rows W -> Y (scatter rows) and C
   nct_status projections(const void* W) {
     if (s->natoms == 0) return NCT_OK;
     nct_status r;
-    if ((r = check(launch_proj_contract<R>(s->pt, W, s->S, s->dV, s->Cpart, s->C, s->EC, s->st),
-                   "proj_contract")) != NCT_OK) return r;
-    return check(launch_proj_scatter<R>(s->pt, s->EC, s->S, s->Y, s->st), "proj_scatter");
+    if ((r = contract(W)) != NCT_OK) return r;
+    const double ecB = double(s->natoms) * s->pt.PP * s->S * sizeof(R) * 2;
+    return check(timed(s, NCT_K_PROJ, beta_bytes() + ecB + rowsB(), proj_flops(), [&] {
+                   return launch_proj_scatter<R>(s->pt, s->EC, s->S, s->Y, s->st); }), "proj_scatter");
   }
 
   void bext_now(double t, R out[3]) {
@@ -470,6 +551,27 @@ struct Engine {
     double B[3];
     bfield_at(s, t, B);
     for (int k = 0; k < 3; ++k) out[k] = R(kMuB * B[k]);
+  }
+
+  nct_status xpass(const void* src, void* dst) {
+    return check(timed(s, NCT_K_XPASS, 2 * psiB(), 0, [&] {
+                   return launch_xpass<R>(s->n, 2 * s->S, src, dst, g2x(), g2yz(), R(0.5 / double(s->N)),
+                                          0, twx(), s->st); }), "xpass");
+  }
+
+  nct_status plane_stage(const StageArgs<R>& sa) {
+    double b = psiB();                                     // tmp_in
+    if (sa.w_in) b += psiB();
+    if (sa.x_base && sa.x_base != sa.w_in) b += psiB();
+    b += 4.0 * s->N * sizeof(R);                           // fields
+    if (sa.Y) b += rowsB();
+    if (sa.w_out) b += psiB();
+    if (sa.tmp_out) b += psiB();
+    if (sa.W) b += rowsB();
+    if (sa.acc) b += 2 * psiB();
+    return check(timed(s, NCT_K_PLANE_STAGE, b, 0, [&] {
+                   return launch_plane_stage<R>(s->n, s->S, sa, s->pt, twy(), twz(), s->st); }),
+                 "plane_stage");
   }
 
   // T_K(-i a H) x by Horner stages w_k = x + (-i a/(K-k+1)) H w_{k-1}, w_0 = x.
@@ -487,9 +589,7 @@ struct Engine {
     for (int k = 1; k <= K; ++k) {
       const bool last = (k == K);
       if ((r = projections(cW)) != NCT_OK) return r;
-      if ((r = check(launch_xpass<R>(s->n, 2 * s->S, chat, s->tmp, g2x(), g2yz(),
-                                     R(0.5 / double(s->N)), 0, twx(), s->st), "xpass")) != NCT_OK)
-        return r;
+      if ((r = xpass(chat, s->tmp)) != NCT_OK) return r;
       sa.tmp_in = s->tmp;
       sa.w_in = cw;
       sa.x_base = x;
@@ -501,8 +601,7 @@ struct Engine {
       sa.tmp_out = last ? outhat : s->tmp;
       sa.W = s->natoms ? (last ? outW : s->Wwork) : nullptr;
       sa.acc = nullptr;
-      if ((r = check(launch_plane_stage<R>(s->n, s->S, sa, s->pt, twy(), twz(), s->st), "plane_stage")) != NCT_OK)
-        return r;
+      if ((r = plane_stage(sa)) != NCT_OK) return r;
       cw = sa.w_out;
       chat = sa.tmp_out;
       cW = sa.W;
@@ -511,19 +610,20 @@ struct Engine {
   }
 
   nct_status prepare(const void* psi, void* hat, void* W) {
-    return check(launch_plane_fwd<R>(s->n, 2 * s->S, psi, hat, s->natoms ? W : nullptr, &s->pt,
-                                     twy(), twz(), s->st), "plane_fwd");
+    return check(timed(s, NCT_K_PLANE_FWD, 2 * psiB() + (s->natoms ? rowsB() : 0.0), 0, [&] {
+                   return launch_plane_fwd<R>(s->n, 2 * s->S, psi, hat, s->natoms ? W : nullptr, &s->pt,
+                                              twy(), twz(), s->st); }), "plane_fwd");
   }
 
   nct_status obs_row(double t, double* row) {
     nct_status r;
     int ntiles = 0;
-    if ((r = check(launch_xpass_energy<R>(s->n, 2 * s->S, s->psihat, g2x(), g2yz(),
-                                          R(0.5 / double(s->N)), twx(), s->epart, &ntiles, s->st),
-                   "energy")) != NCT_OK) return r;
+    if ((r = check(timed(s, NCT_K_OBS, psiB(), 0, [&] {
+           return launch_xpass_energy<R>(s->n, 2 * s->S, s->psihat, g2x(), g2yz(), R(0.5 / double(s->N)),
+                                         twx(), s->epart, &ntiles, s->st); }), "energy")) != NCT_OK)
+      return r;
     if (s->natoms) {
-      if ((r = check(launch_proj_contract<R>(s->pt, s->Wpsi, s->S, s->dV, s->Cpart, s->C, s->EC, s->st),
-                     "proj_contract")) != NCT_OK) return r;
+      if ((r = contract(s->Wpsi)) != NCT_OK) return r;
     }
     ObsInputs in;
     in.field_tot = s->ftot;
@@ -542,7 +642,7 @@ struct Engine {
     double B[3] = {0, 0, 0};
     if (!s->frozen) bfield_at(s, t, B);
     for (int k = 0; k < 3; ++k) in.muB_B[k] = kMuB * B[k];
-    return check(launch_obs_row(in, row, s->st), "obs_row");
+    return check(timed(s, NCT_K_OBS, 0, 0, [&] { return launch_obs_row(in, row, s->st); }), "obs_row");
   }
 
   nct_status step(void* psi, double t0, int nsteps, double* obs_host) {
@@ -582,6 +682,7 @@ struct Engine {
       HIPCHK(s, hipMemcpyAsync(obs_host, s->obs_dev, size_t(nsteps) * kObsWidth * sizeof(double),
                                hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
+    harvest_timing(s);
     if ((!s->frozen || obs_host) && !std::isfinite(tot[0]))
       return fail(s, NCT_ERR_NONFINITE, "non-finite electron count after step");
     return NCT_OK;
@@ -591,9 +692,7 @@ struct Engine {
     nct_status r;
     if ((r = prepare(psi, s->tmp, s->Wwork)) != NCT_OK) return r;
     if ((r = projections(s->Wwork)) != NCT_OK) return r;
-    if ((r = check(launch_xpass<R>(s->n, 2 * s->S, s->tmp, s->tmp, g2x(), g2yz(),
-                                   R(0.5 / double(s->N)), 0, twx(), s->st), "xpass")) != NCT_OK)
-      return r;
+    if ((r = xpass(s->tmp, s->tmp)) != NCT_OK) return r;
     StageArgs<R> sa;
     bext_now(t, sa.bext);
     sa.fields = fieldsR();
@@ -605,7 +704,7 @@ struct Engine {
     sa.cim = R(0);
     sa.Y = s->natoms ? s->Y : nullptr;
     sa.w_out = hpsi;
-    return check(launch_plane_stage<R>(s->n, s->S, sa, s->pt, twy(), twz(), s->st), "plane_stage");
+    return plane_stage(sa);
   }
 };
 
@@ -772,6 +871,9 @@ nct_status nct_create_system(const nct_params* params, nct_system** out) {
 void nct_destroy_system(nct_system* sys) {
   if (!sys) return;
   (void)hipStreamSynchronize(sys->st);
+  harvest_timing(sys);
+  for (hipEvent_t e : sys->free_events) (void)hipEventDestroy(e);
+  sys->free_events.clear();
   free_all(sys);
   delete sys;
 }
@@ -878,6 +980,33 @@ nct_status nct_backward_step(nct_system* s, int tape_index, const void* psi_n, d
   (void)tape_index; (void)psi_n; (void)t_n; (void)lam_np1; (void)lam_n; (void)dLdB; (void)dLdtheta;
   if (!s) return NCT_ERR_ARG;
   return fail(s, NCT_ERR_UNSUPPORTED, "adjoint not available in this build");
+}
+
+nct_status nct_set_timing(nct_system* s, int enable) {
+  if (!s) return NCT_ERR_ARG;
+  HIPCHK(s, hipStreamSynchronize(s->st));
+  harvest_timing(s);
+  for (int k = 0; k < NCT_K_COUNT; ++k) {
+    s->t_ms[k] = 0;
+    s->t_count[k] = 0;
+    s->t_bytes[k] = 0;
+    s->t_flops[k] = 0;
+  }
+  s->timing = enable != 0;
+  return NCT_OK;
+}
+
+nct_status nct_get_timing(nct_system* s, int k, double* ms, long long* launches, double* bytes,
+                          double* flops) {
+  if (!s) return NCT_ERR_ARG;
+  if (k < 0 || k >= NCT_K_COUNT) return fail(s, NCT_ERR_ARG, "kernel class out of range");
+  HIPCHK(s, hipStreamSynchronize(s->st));
+  harvest_timing(s);
+  if (ms) *ms = s->t_ms[k];
+  if (launches) *launches = s->t_count[k];
+  if (bytes) *bytes = s->t_bytes[k];
+  if (flops) *flops = s->t_flops[k];
+  return NCT_OK;
 }
 
 const char* nct_version(void) {

@@ -20,6 +20,7 @@ NCT_OK, NCT_ERR_ARG, NCT_ERR_UNSUPPORTED, NCT_ERR_OOM, NCT_ERR_HIP, NCT_ERR_NONF
 NCT_FP64, NCT_FP32_MIXED = 0, 1
 STATUS_NAMES = {0: "NCT_OK", 1: "NCT_ERR_ARG", 2: "NCT_ERR_UNSUPPORTED", 3: "NCT_ERR_OOM",
                 4: "NCT_ERR_HIP", 5: "NCT_ERR_NONFINITE", 6: "NCT_ERR_STATE"}
+KERNEL_CLASSES = ["plane_stage", "xpass", "plane_fwd", "density", "fields", "proj", "obs", "adjoint"]
 OBS_NAMES = ["t", "N_e", "M_x", "M_y", "M_z", "E_total", "E_kin", "E_loc", "E_NL", "E_H",
              "E_xc", "E_Z", "max_norm_err"]
 
@@ -84,6 +85,11 @@ def lib():
         L.nct_backward_step.argtypes = [c_void_p, c_int, c_void_p, c_double, c_void_p, c_void_p,
                                         POINTER(c_double), POINTER(c_double)]
         L.nct_backward_step.restype = c_int
+        L.nct_set_timing.argtypes = [c_void_p, c_int]
+        L.nct_set_timing.restype = c_int
+        L.nct_get_timing.argtypes = [c_void_p, c_int, POINTER(c_double), POINTER(ctypes.c_longlong),
+                                     POINTER(c_double), POINTER(c_double)]
+        L.nct_get_timing.restype = c_int
         L.nct_version.argtypes = []
         L.nct_version.restype = ctypes.c_char_p
         _LIB = L
@@ -228,6 +234,19 @@ class System:
                                             _tptr(lam_np1), _tptr(lam_n), _dptr(dLdB),
                                             _dptr(dLdtheta) if dLdtheta is not None else None))
         return dLdB
+
+    def set_timing(self, enable: bool):
+        self._check(lib().nct_set_timing(self.h, int(enable)))
+
+    def timing(self):
+        """{class: (ms, launches, algorithmic bytes, flops)} since the last set_timing."""
+        out = {}
+        for k, name in enumerate(KERNEL_CLASSES):
+            ms, cnt, by, fl = c_double(), ctypes.c_longlong(), c_double(), c_double()
+            self._check(lib().nct_get_timing(self.h, k, ctypes.byref(ms), ctypes.byref(cnt),
+                                             ctypes.byref(by), ctypes.byref(fl)))
+            out[name] = (ms.value, cnt.value, by.value, fl.value)
+        return out
 
 
 def system_from_workload(w, precision: int = NCT_FP64, tape_steps: int = 0, dt=None,
