@@ -98,6 +98,26 @@ struct nct_system {
   void* EC = nullptr;
   double* energy_dev = nullptr;
 
+  // adjoint tape: per step 3K state vectors (Taylor iterates of the three exponentials,
+  // psi_n, phi, psi~) and the densities / fields of H_n and H~
+  struct Tape {
+    int cap = 0;
+    int valid = 0;
+    double t0 = 0.0;
+    void* vec = nullptr;      // [cap][3K] states
+    double* rho = nullptr;    // [cap][2][4N]  rho(psi_n), rho(psi~)
+    double* fld = nullptr;    // [cap][2][4N]  fields of H_n, H~ (without B_ext)
+  };
+  Tape tape;
+  Tape scratch_tape;          // one step, for recompute mode
+  void* scratch_out = nullptr;
+  double* gA = nullptr;       // [4][N] field gradients
+  double* gB = nullptr;
+  double* gnm = nullptr;      // [4][N] density gradients
+  double* pg = nullptr;       // [N] Poisson of g_v
+  double* gpart = nullptr;    // [nblk][4]
+  double* gtot = nullptr;     // [4]
+
   // kernel timing (profiling aid)
   struct TimedLaunch {
     int k;
@@ -575,8 +595,9 @@ struct Engine {
   }
 
   // T_K(-i a H) x by Horner stages w_k = x + (-i a/(K-k+1)) H w_{k-1}, w_0 = x.
+  // stage_out[k-1] (k = 1..K-1), if given, receives w_k (the adjoint tape); else the work buffer.
   nct_status taylor(const void* x, const void* xhat, const void* xW, void* out, void* outhat,
-                    void* outW, double t) {
+                    void* outW, double t, void* const* stage_out = nullptr) {
     const int K = s->prm.taylor_order;
     const double a = 0.5 * s->prm.dt;
     const void* cw = x;
@@ -597,7 +618,7 @@ struct Engine {
       sa.cre = R(0);
       sa.cim = R(-a / double(K - k + 1));
       sa.Y = s->natoms ? s->Y : nullptr;
-      sa.w_out = last ? out : s->wbuf;
+      sa.w_out = last ? out : (stage_out ? stage_out[k - 1] : s->wbuf);
       sa.tmp_out = last ? outhat : s->tmp;
       sa.W = s->natoms ? (last ? outW : s->Wwork) : nullptr;
       sa.acc = nullptr;
@@ -645,12 +666,40 @@ struct Engine {
     return check(timed(s, NCT_K_OBS, 0, 0, [&] { return launch_obs_row(in, row, s->st); }), "obs_row");
   }
 
-  nct_status step(void* psi, double t0, int nsteps, double* obs_host) {
+  void* tvec(nct_system::Tape& T, int step, int j) const {
+    const int K = s->prm.taylor_order;
+    const size_t psib = size_t(psiB());
+    return static_cast<char*>(T.vec) + (size_t(step) * 3 * K + j) * psib;
+  }
+  double* trho(nct_system::Tape& T, int step, int which) const {
+    return T.rho + (size_t(step) * 2 + which) * 4 * s->N;
+  }
+  double* tfld(nct_system::Tape& T, int step, int which) const {
+    return T.fld + (size_t(step) * 2 + which) * 4 * s->N;
+  }
+  nct_status save_fields(nct_system::Tape& T, int step, int which) {
+    HIPCHK(s, hipMemcpyAsync(trho(T, step, which), s->rho, 4 * s->N * 8, hipMemcpyDeviceToDevice, s->st));
+    HIPCHK(s, hipMemcpyAsync(tfld(T, step, which), s->fields, 4 * s->N * 8, hipMemcpyDeviceToDevice, s->st));
+    return NCT_OK;
+  }
+
+  // nsteps ETRS steps.  With a tape, step k's Taylor iterates are written straight into the tape
+  // (slots: exp 1 -> 0..K-1 with slot 0 = psi_n, exp 2 -> K..2K-1 with slot K = phi,
+  // exp 3 -> 2K..3K-2, slot 3K-1 = psi~); psi_{n+1} lands in slot 0 of step n+1.
+  nct_status step(void* psi, double t0, int nsteps, double* obs_host, nct_system::Tape* T = nullptr) {
     nct_status r;
     const double dt = s->prm.dt;
-    if ((r = prepare(psi, s->psihat, s->Wpsi)) != NCT_OK) return r;
+    const int K = s->prm.taylor_order;
+    void* cur = psi;
+    if (T) {
+      HIPCHK(s, hipMemcpyAsync(tvec(*T, 0, 0), psi, size_t(psiB()), hipMemcpyDeviceToDevice, s->st));
+      cur = tvec(*T, 0, 0);
+      T->valid = 0;
+      T->t0 = t0;
+    }
+    if ((r = prepare(cur, s->psihat, s->Wpsi)) != NCT_OK) return r;
     if (!s->frozen) {
-      if ((r = density(psi)) != NCT_OK) return r;
+      if ((r = density(cur)) != NCT_OK) return r;
       if ((r = fields_from_rho(true)) != NCT_OK) return r;
     }
     if (obs_host && s->obs_cap < nsteps) {
@@ -659,17 +708,37 @@ struct Engine {
       s->obs_dev = static_cast<double*>(p);
       s->obs_cap = nsteps;
     }
+    std::vector<void*> so1(K > 1 ? K - 1 : 1), so2(K > 1 ? K - 1 : 1), so3(K > 1 ? K - 1 : 1);
     for (int k = 0; k < nsteps; ++k) {
       const double t = t0 + k * dt;
-      if ((r = taylor(psi, s->psihat, s->Wpsi, s->phi, s->phihat, s->Wphi, t)) != NCT_OK) return r;
-      if ((r = taylor(s->phi, s->phihat, s->Wphi, s->wbuf, nullptr, nullptr, t)) != NCT_OK) return r;
+      void* phi = s->phi;
+      void* ptil = s->wbuf;
+      void* next = psi;
+      if (T) {
+        if ((r = save_fields(*T, k, 0)) != NCT_OK) return r;
+        for (int j = 1; j < K; ++j) {
+          so1[j - 1] = tvec(*T, k, j);
+          so2[j - 1] = tvec(*T, k, K + j);
+          so3[j - 1] = tvec(*T, k, 2 * K + j - 1);
+        }
+        phi = tvec(*T, k, K);
+        ptil = tvec(*T, k, 3 * K - 1);
+        next = (k + 1 < nsteps) ? tvec(*T, k + 1, 0) : psi;
+      }
+      if ((r = taylor(cur, s->psihat, s->Wpsi, phi, s->phihat, s->Wphi, t, T ? so1.data() : nullptr)) != NCT_OK)
+        return r;
+      if ((r = taylor(phi, s->phihat, s->Wphi, ptil, nullptr, nullptr, t, T ? so2.data() : nullptr)) != NCT_OK)
+        return r;
       if (!s->frozen) {
-        if ((r = density(s->wbuf)) != NCT_OK) return r;
+        if ((r = density(ptil)) != NCT_OK) return r;
         if ((r = fields_from_rho(true)) != NCT_OK) return r;
       }
-      if ((r = taylor(s->phi, s->phihat, s->Wphi, psi, s->psihat, s->Wpsi, t + dt)) != NCT_OK) return r;
+      if (T && (r = save_fields(*T, k, 1)) != NCT_OK) return r;
+      if ((r = taylor(phi, s->phihat, s->Wphi, next, s->psihat, s->Wpsi, t + dt, T ? so3.data() : nullptr)) != NCT_OK)
+        return r;
+      cur = next;
       if (!s->frozen || obs_host) {
-        if ((r = density(psi)) != NCT_OK) return r;
+        if ((r = density(cur)) != NCT_OK) return r;
         if ((r = fields_from_rho(!s->frozen)) != NCT_OK) return r;
       }
       if (obs_host) {
@@ -683,8 +752,153 @@ struct Engine {
                                hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     harvest_timing(s);
+    if (T) T->valid = nsteps;
     if ((!s->frozen || obs_host) && !std::isfinite(tot[0]))
       return fail(s, NCT_ERR_NONFINITE, "non-finite electron count after step");
+    return NCT_OK;
+  }
+
+  // ------------------------------------------------------------ adjoint
+  nct_status load_fields(const double* f64) {
+    HIPCHK(s, hipMemcpyAsync(s->fields, f64, 4 * s->N * 8, hipMemcpyDeviceToDevice, s->st));
+    if (!s->fp64) HIPCHK(s, launch_to_float(s->fields, 4 * s->N, s->fields32, s->st));
+    return NCT_OK;
+  }
+
+  // Adjoint of one Taylor exponential w_K = T(-i a H) x (Horner stages, fields frozen):
+  // given mu_K = lam_out, mu_{k-1} = conj(c_k) H mu_k, lam_x = sum_{k=0}^{K} mu_k (into acc,
+  // which is set to mu_K first when acc_init, else mu_K is added), and for each stage the pair
+  // term of dL/d(v, b) into g.  xs[k] = w_k (k = 0..K-1) from the forward tape.
+  nct_status adjoint_taylor(const void* lam_out, void* const* xs, void* acc, bool acc_init, double* g,
+                            double t) {
+    nct_status r;
+    const int K = s->prm.taylor_order;
+    const double a = 0.5 * s->prm.dt;
+    const size_t cnt = size_t(s->S) * 2 * s->N;
+    if (acc_init) {
+      HIPCHK(s, hipMemcpyAsync(acc, lam_out, size_t(psiB()), hipMemcpyDeviceToDevice, s->st));
+    } else {
+      if ((r = check(timed(s, NCT_K_ADJOINT, 3 * psiB(), 0, [&] {
+             return launch_axpby<R>(acc, lam_out, cnt, R(1), R(0), R(1), s->st); }), "axpby")) != NCT_OK)
+        return r;
+    }
+    if ((r = prepare(lam_out, s->tmp, s->Wwork)) != NCT_OK) return r;
+    StageArgs<R> sa;
+    bext_now(t, sa.bext);
+    sa.fields = fieldsR();
+    const void* cur = lam_out;
+    for (int k = K; k >= 1; --k) {
+      const double gamma = a / double(K - k + 1);
+      if ((r = check(timed(s, NCT_K_ADJOINT, 2 * psiB() + 64.0 * s->N, 0, [&] {
+             return launch_pair<R>(cur, xs[k - 1], s->S, s->N, gamma, g, s->st); }), "pair")) != NCT_OK)
+        return r;
+      if ((r = projections(s->Wwork)) != NCT_OK) return r;
+      if ((r = xpass(s->tmp, s->tmp)) != NCT_OK) return r;
+      sa.tmp_in = s->tmp;
+      sa.w_in = cur;
+      sa.x_base = nullptr;
+      sa.alpha = R(0);
+      sa.cre = R(0);
+      sa.cim = R(gamma);
+      sa.Y = s->natoms ? s->Y : nullptr;
+      sa.w_out = s->wbuf;
+      sa.tmp_out = k > 1 ? s->tmp : nullptr;
+      sa.W = (s->natoms && k > 1) ? s->Wwork : nullptr;
+      sa.acc = acc;
+      if ((r = plane_stage(sa)) != NCT_OK) return r;
+      cur = s->wbuf;
+    }
+    return NCT_OK;
+  }
+
+  // (g_v, g_b) at the fields of density rho  ->  (g_n, g_m) into s->gnm; returns sum_r g_b in gsum.
+  nct_status field_adjoint(const double* rho, const double* g, double gsum[3]) {
+    nct_status r;
+    const double N = double(s->N);
+    const double* pgp = nullptr;
+    if (s->prm.hartree) {
+      if ((r = check(timed(s, NCT_K_ADJOINT, 24 * N, 0, [&] { return launch_real_to_cpx(g, s->N, s->ncpx, s->st); }),
+                     "real_to_cpx")) != NCT_OK) return r;
+      if ((r = check(timed(s, NCT_K_ADJOINT, 32 * N, 0, [&] {
+             return launch_plane_fwd<double>(s->n, 1, s->ncpx, s->ncpx, nullptr, nullptr, s->tw64[1],
+                                             s->tw64[2], s->st); }), "adj poisson fwd")) != NCT_OK) return r;
+      if ((r = check(timed(s, NCT_K_ADJOINT, 32 * N, 0, [&] {
+             return launch_xpass<double>(s->n, 1, s->ncpx, s->ncpx, s->g2x64, s->g2yz64,
+                                         4.0 * kPi / double(s->N), 1, s->tw64[0], s->st); }),
+                     "adj poisson x")) != NCT_OK) return r;
+      if ((r = check(timed(s, NCT_K_ADJOINT, 32 * N, 0, [&] {
+             return launch_plane_inv<double>(s->n, 1, s->ncpx, s->ncpx, 1.0, s->tw64[1], s->tw64[2],
+                                             s->st); }), "adj poisson inv")) != NCT_OK) return r;
+      if ((r = check(timed(s, NCT_K_ADJOINT, 24 * N, 0, [&] { return launch_cpx_real(s->ncpx, s->N, s->pg, s->st); }),
+                     "adj cpx_real")) != NCT_OK) return r;
+      pgp = s->pg;
+    }
+    int nb = 0;
+    if ((r = check(timed(s, NCT_K_ADJOINT, 96 * N, 0, [&] {
+           return launch_field_adjoint(rho, g, pgp, s->prm.xc, s->prm.m_threshold, s->N, s->gnm, s->gpart,
+                                       &nb, s->st); }), "field_adjoint")) != NCT_OK) return r;
+    if ((r = check(launch_reduce_rows(s->gpart, nb, 4, s->gtot, s->st), "reduce")) != NCT_OK) return r;
+    double tot[4];
+    HIPCHK(s, hipMemcpyAsync(tot, s->gtot, sizeof(tot), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    for (int k = 0; k < 3; ++k) gsum[k] = tot[k];
+    return NCT_OK;
+  }
+
+  nct_status backprop_density(const void* psi, void* lam, int add) {
+    return check(timed(s, NCT_K_ADJOINT, (add ? 3 : 2) * psiB() + 32.0 * s->N, 0, [&] {
+                   return launch_density_backprop<R>(psi, s->occ, s->gnm, s->S, s->N, add, lam, s->st); }),
+                 "density_backprop");
+  }
+
+  // Reverse of one ETRS step (see the forward step for the tape slots).
+  nct_status backward(nct_system::Tape& T, int idx, double t_n, const void* lam_np1, void* lam_n,
+                      double dLdB[6]) {
+    nct_status r;
+    const int K = s->prm.taylor_order;
+    const double dt = s->prm.dt;
+    const size_t gb = 4 * s->N * 8;
+    std::vector<void*> xs1(K), xs2(K), xs3(K);
+    xs1[0] = tvec(T, idx, 0);
+    xs2[0] = tvec(T, idx, K);
+    xs3[0] = tvec(T, idx, K);
+    for (int j = 1; j < K; ++j) {
+      xs1[j] = tvec(T, idx, j);
+      xs2[j] = tvec(T, idx, K + j);
+      xs3[j] = tvec(T, idx, 2 * K + j - 1);
+    }
+    void* lamphi = s->phi;
+    void* lamtil = s->phihat;
+    double gs[3] = {0, 0, 0};
+    // third exponential, fields of H~ at t_{n+1}
+    if ((r = load_fields(tfld(T, idx, 1))) != NCT_OK) return r;
+    HIPCHK(s, hipMemsetAsync(s->gA, 0, gb, s->st));
+    if ((r = adjoint_taylor(lam_np1, xs3.data(), lamphi, true, s->gA, t_n + dt)) != NCT_OK) return r;
+    if (s->frozen) {
+      for (int k = 0; k < 6; ++k) dLdB[k] = 0.0;
+    } else {
+      if ((r = field_adjoint(trho(T, idx, 1), s->gA, gs)) != NCT_OK) return r;
+      for (int k = 0; k < 3; ++k) dLdB[3 + k] = kMuB * gs[k];
+      // density at psi~ -> lam_psi~, then the second exponential (fields of H_n)
+      if ((r = backprop_density(tvec(T, idx, 3 * K - 1), lamtil, 0)) != NCT_OK) return r;
+      if ((r = load_fields(tfld(T, idx, 0))) != NCT_OK) return r;
+      HIPCHK(s, hipMemsetAsync(s->gB, 0, gb, s->st));
+      if ((r = adjoint_taylor(lamtil, xs2.data(), lamphi, false, s->gB, t_n)) != NCT_OK) return r;
+    }
+    if (s->frozen) {
+      HIPCHK(s, hipMemsetAsync(s->gB, 0, gb, s->st));
+    } else {
+      if ((r = load_fields(tfld(T, idx, 0))) != NCT_OK) return r;
+    }
+    // first exponential -> lam_n
+    if ((r = adjoint_taylor(lamphi, xs1.data(), lam_n, true, s->gB, t_n)) != NCT_OK) return r;
+    if (!s->frozen) {
+      if ((r = field_adjoint(trho(T, idx, 0), s->gB, gs)) != NCT_OK) return r;
+      for (int k = 0; k < 3; ++k) dLdB[k] = kMuB * gs[k];
+      if ((r = backprop_density(tvec(T, idx, 0), lam_n, 1)) != NCT_OK) return r;
+    }
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    harvest_timing(s);
     return NCT_OK;
   }
 
@@ -748,6 +962,21 @@ nct_status build_fft_tables(nct_system* s) {
   if ((r = upload(s, gyz, &s->g2yz64)) != NCT_OK) return r;
   if ((r = upload(s, gx32, &s->g2x32)) != NCT_OK) return r;
   if ((r = upload(s, gyz32, &s->g2yz32)) != NCT_OK) return r;
+  return NCT_OK;
+}
+
+nct_status alloc_tape(nct_system* s, nct_system::Tape& T, int cap) {
+  const size_t psib = size_t(s->S) * 2 * s->N * s->cbytes;
+  const int K = s->prm.taylor_order;
+  nct_status r;
+  void* p;
+  if ((r = dalloc(s, size_t(cap) * 3 * K * psib, &T.vec)) != NCT_OK) return r;
+  if ((r = dalloc(s, size_t(cap) * 2 * 4 * s->N * 8, &p)) != NCT_OK) return r;
+  T.rho = static_cast<double*>(p);
+  if ((r = dalloc(s, size_t(cap) * 2 * 4 * s->N * 8, &p)) != NCT_OK) return r;
+  T.fld = static_cast<double*>(p);
+  T.cap = cap;
+  T.valid = 0;
   return NCT_OK;
 }
 
@@ -844,6 +1073,19 @@ nct_status create_impl(const nct_params* p, nct_system** out) {
   if (s->fp64) r = build_projectors<double>(s);
   else r = build_projectors<float>(s);
   if (r != NCT_OK) return bail(r);
+  if ((r = dalloc(s, 4 * N * 8, &p0)) != NCT_OK) return bail(r);
+  s->gA = (double*)p0;
+  if ((r = dalloc(s, 4 * N * 8, &p0)) != NCT_OK) return bail(r);
+  s->gB = (double*)p0;
+  if ((r = dalloc(s, 4 * N * 8, &p0)) != NCT_OK) return bail(r);
+  s->gnm = (double*)p0;
+  if ((r = dalloc(s, N * 8, &p0)) != NCT_OK) return bail(r);
+  s->pg = (double*)p0;
+  if ((r = dalloc(s, ((N + 255) / 256) * 4 * 8, &p0)) != NCT_OK) return bail(r);
+  s->gpart = (double*)p0;
+  if ((r = dalloc(s, 4 * 8, &p0)) != NCT_OK) return bail(r);
+  s->gtot = (double*)p0;
+  if (p->tape_steps > 0 && (r = alloc_tape(s, s->tape, p->tape_steps)) != NCT_OK) return bail(r);
   hipError_t e = hipMemsetAsync(s->vext, 0, N * 8, s->st);
   if (e == hipSuccess) e = hipMemsetAsync(s->fields, 0, 4 * N * 8, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
@@ -959,11 +1201,12 @@ nct_status nct_step(nct_system* s, void* psi, double t0, int nsteps, double* obs
   if (!s || !psi) return s ? fail(s, NCT_ERR_ARG, "psi is NULL") : NCT_ERR_ARG;
   if (nsteps < 0) return fail(s, NCT_ERR_ARG, "nsteps < 0");
   if (tape && nsteps > s->prm.tape_steps) return fail(s, NCT_ERR_ARG, "nsteps exceeds tape_steps");
-  if (tape) return fail(s, NCT_ERR_UNSUPPORTED, "tape not available in this build");
   if (nsteps == 0) return NCT_OK;
   if (s->frozen && !s->fields_valid) return fail(s, NCT_ERR_STATE, "no fields");
-  if (s->fp64) return Engine<double>{s}.step(psi, t0, nsteps, obs_host);
-  return Engine<float>{s}.step(psi, t0, nsteps, obs_host);
+  nct_system::Tape* T = tape ? &s->tape : nullptr;
+  if (T) T->valid = 0;
+  if (s->fp64) return Engine<double>{s}.step(psi, t0, nsteps, obs_host, T);
+  return Engine<float>{s}.step(psi, t0, nsteps, obs_host, T);
 }
 
 nct_status nct_magnetization_seed(nct_system* s, const void* psi, const double* w, void* lam) {
@@ -977,9 +1220,54 @@ nct_status nct_magnetization_seed(nct_system* s, const void* psi, const double* 
 
 nct_status nct_backward_step(nct_system* s, int tape_index, const void* psi_n, double t_n,
                              const void* lam_np1, void* lam_n, double* dLdB, double* dLdtheta) {
-  (void)tape_index; (void)psi_n; (void)t_n; (void)lam_np1; (void)lam_n; (void)dLdB; (void)dLdtheta;
   if (!s) return NCT_ERR_ARG;
-  return fail(s, NCT_ERR_UNSUPPORTED, "adjoint not available in this build");
+  if (!lam_np1 || !lam_n) return fail(s, NCT_ERR_ARG, "lam_np1 / lam_n is NULL");
+  if (s->frozen && !s->fields_valid) return fail(s, NCT_ERR_STATE, "no fields");
+  nct_system::Tape* T = nullptr;
+  int idx = 0;
+  nct_status r;
+  if (tape_index >= 0) {
+    if (tape_index >= s->tape.valid)
+      return fail(s, NCT_ERR_STATE, "tape index %d not recorded (tape holds %d steps)", tape_index,
+                  s->tape.valid);
+    const double tt = s->tape.t0 + tape_index * s->prm.dt;
+    if (std::fabs(tt - t_n) > 1e-9 * std::max(1.0, std::fabs(tt)))
+      return fail(s, NCT_ERR_ARG, "t_n = %g does not match the taped time %g", t_n, tt);
+    T = &s->tape;
+    idx = tape_index;
+  } else {
+    if (!psi_n) return fail(s, NCT_ERR_ARG, "psi_n is NULL in recompute mode");
+    if (s->scratch_tape.cap == 0) {
+      if ((r = alloc_tape(s, s->scratch_tape, 1)) != NCT_OK) return r;
+      if ((r = dalloc(s, size_t(s->S) * 2 * s->N * s->cbytes, &s->scratch_out)) != NCT_OK) return r;
+    }
+    HIPCHK(s, hipMemcpyAsync(s->scratch_out, psi_n, size_t(s->S) * 2 * s->N * s->cbytes,
+                             hipMemcpyDeviceToDevice, s->st));
+    if (s->fp64) r = Engine<double>{s}.step(s->scratch_out, t_n, 1, nullptr, &s->scratch_tape);
+    else r = Engine<float>{s}.step(s->scratch_out, t_n, 1, nullptr, &s->scratch_tape);
+    if (r != NCT_OK) return r;
+    T = &s->scratch_tape;
+    idx = 0;
+  }
+  double dB[6] = {0, 0, 0, 0, 0, 0};
+  if (s->fp64) r = Engine<double>{s}.backward(*T, idx, t_n, lam_np1, lam_n, dB);
+  else r = Engine<float>{s}.backward(*T, idx, t_n, lam_np1, lam_n, dB);
+  if (r != NCT_OK) return r;
+  // the system's fields now hold those of H_n; mark them current for later H applications
+  s->fields_valid = true;
+  if (dLdB)
+    for (int k = 0; k < 6; ++k) dLdB[k] = dB[k];
+  if (dLdtheta && !s->pulses.empty()) {
+    std::vector<double> j0, j1;
+    bfield_jac(s, t_n, j0);
+    bfield_jac(s, t_n + s->prm.dt, j1);
+    const size_t np = 2 * s->pulses.size();
+    for (size_t q = 0; q < np; ++q)
+      for (int k = 0; k < 3; ++k) dLdtheta[q] += dB[k] * j0[q * 3 + k] + dB[3 + k] * j1[q * 3 + k];
+  }
+  for (int k = 0; k < 6; ++k)
+    if (!std::isfinite(dB[k])) return fail(s, NCT_ERR_NONFINITE, "non-finite field gradient");
+  return NCT_OK;
 }
 
 nct_status nct_set_timing(nct_system* s, int enable) {

@@ -117,6 +117,18 @@ template <typename R>
 hipError_t launch_axpby(void* y, const void* x, size_t count, R a_re, R a_im, R b,
                         hipStream_t st);
 
+// Adjoint kernels
+template <typename R>
+hipError_t launch_pair(const void* mu, const void* w, int S, size_t N, double gamma, double* g,
+                       hipStream_t st);
+hipError_t launch_field_adjoint(const double* rho, const double* g, const double* pg, int xc,
+                                double thr, size_t N, double* gnm, double* part, int* nblk_out,
+                                hipStream_t st);
+template <typename R>
+hipError_t launch_density_backprop(const void* psi, const double* occ, const double* gnm, int S,
+                                   size_t N, int add, void* lam, hipStream_t st);
+hipError_t launch_real_to_cpx(const double* r, size_t N, void* out, hipStream_t st);
+
 bool plane_pair_supported(int ny, int nz);
 bool line_supported(int n);
 

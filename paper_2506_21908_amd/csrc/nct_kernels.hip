@@ -623,6 +623,138 @@ __global__ __launch_bounds__(64) void k_proj_scatter(ProjTables pt, const cpx<R>
   }
 }
 
+// ---------------------------------------------------------------- adjoint kernels
+// Pair reduction of one adjoint Taylor stage:
+//   g[0][p] += gamma sum_i Im(mu_i^dagger w_i),  g[1+q][p] += gamma sum_i Im(mu_i^dagger sigma_q w_i)
+// i.e. dL = sum_r (g_v dv + g_b . db) for a perturbation dH = dv + db.sigma of the stage
+// w_k = x + (-i gamma) H w_{k-1} with adjoint mu_k.
+template <typename R>
+__global__ __launch_bounds__(256) void k_pair(const cpx<R>* __restrict__ mu, const cpx<R>* __restrict__ w,
+                                              int S, size_t N, double gamma, double* __restrict__ g) {
+  const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p >= N) return;
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll 2
+  for (int i = 0; i < S; ++i) {
+    const cpx<R> mu_u = mu[size_t(2 * i) * N + p], mu_d = mu[size_t(2 * i + 1) * N + p];
+    const cpx<R> w_u = w[size_t(2 * i) * N + p], w_d = w[size_t(2 * i + 1) * N + p];
+    const double ar = mu_u.x, ai = mu_u.y, br = mu_d.x, bi = mu_d.y;
+    const double ur = w_u.x, ui = w_u.y, dr = w_d.x, di = w_d.y;
+    // Im(conj(a) u) = ar ui - ai ur
+    const double im_au = ar * ui - ai * ur, im_bd = br * di - bi * dr;
+    const double im_ad = ar * di - ai * dr, im_bu = br * ui - bi * ur;
+    const double re_ad = ar * dr + ai * di, re_bu = br * ur + bi * ui;
+    s0 += im_au + im_bd;                 // 1
+    s1 += im_ad + im_bu;                 // sigma_x: conj(a) d + conj(b) u
+    s2 += -re_ad + re_bu;                // sigma_y: -i conj(a) d + i conj(b) u  -> Im = -Re(a*d) + Re(b*u)
+    s3 += im_au - im_bd;                 // sigma_z
+  }
+  g[p] += gamma * s0;
+  g[N + p] += gamma * s1;
+  g[2 * N + p] += gamma * s2;
+  g[3 * N + p] += gamma * s3;
+}
+
+// Transpose of the field map (v, b) <- (n, m) at the density rho, for gradients g = (g_v, g_b):
+//   g_n = P g_v + dvbar/dn g_v + dbeta/dn (mhat.g_b)
+//   g_m = [dvbar/dmu g_v + dbeta/dmu (mhat.g_b)] mhat + (beta/mu)(g_b - mhat (mhat.g_b))
+// with beta = (v_up - v_dn)/2, v_s' = -(1/3)(6/pi)^(1/3) n_s^(-2/3) (0 on a clamped channel),
+// b_xc = 0 (and its derivatives) below the |m| threshold.  pg = P g_v (Poisson) or null.
+// part[blk][0..2] = block sums of g_b (for dL/dB_ext).
+__global__ __launch_bounds__(256) void k_field_adjoint(const double* __restrict__ rho,
+                                                       const double* __restrict__ g,
+                                                       const double* __restrict__ pg, int xc,
+                                                       double thr, size_t N, double* __restrict__ gnm,
+                                                       double* __restrict__ part) {
+  __shared__ double red[4];
+  const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
+  double gbx = 0, gby = 0, gbz = 0;
+  if (p < N) {
+    const double gv = g[p];
+    gbx = g[N + p];
+    gby = g[2 * N + p];
+    gbz = g[3 * N + p];
+    double gn = pg ? pg[p] : 0.0;
+    double gmx = 0, gmy = 0, gmz = 0;
+    if (xc) {
+      const double c = 1.2407009817988000;  // (6/pi)^(1/3)
+      const double ruu = rho[p], rdd = rho[N + p], rr = rho[2 * N + p], ri = rho[3 * N + p];
+      const double n = ruu + rdd, mx = 2.0 * rr, my = -2.0 * ri, mz = ruu - rdd;
+      const double mu = sqrt(mx * mx + my * my + mz * mz);
+      const double nu = 0.5 * (n + mu), nd = 0.5 * (n - mu);
+      const double cu = nu > 0 ? cbrt(nu) : 0.0, cd = nd > 0 ? cbrt(nd) : 0.0;
+      const double du = nu > 0 ? -(c / 3.0) / (cu * cu) : 0.0;
+      const double dd = nd > 0 ? -(c / 3.0) / (cd * cd) : 0.0;
+      gn += 0.25 * (du + dd) * gv;
+      if (mu >= thr) {
+        const double hx = mx / mu, hy = my / mu, hz = mz / mu;
+        const double mg = hx * gbx + hy * gby + hz * gbz;
+        const double nuc = fmax(nu, 0.0), ndc = fmax(nd, 0.0);
+        const double den = cu * cu + cu * cd + cd * cd;
+        const double bmag = den > 0.0 ? -0.5 * c * (nuc - ndc) / den : 0.0;
+        const double bom = bmag / mu;
+        gn += 0.25 * (du - dd) * mg;
+        const double radial = 0.25 * (du - dd) * gv + 0.25 * (du + dd) * mg;
+        gmx = radial * hx + bom * (gbx - hx * mg);
+        gmy = radial * hy + bom * (gby - hy * mg);
+        gmz = radial * hz + bom * (gbz - hz * mg);
+      }
+    }
+    gnm[p] = gn;
+    gnm[N + p] = gmx;
+    gnm[2 * N + p] = gmy;
+    gnm[3 * N + p] = gmz;
+  }
+  const double v3[3] = {gbx, gby, gbz};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double t = block_sum<256>(v3[k], red);
+    if (threadIdx.x == 0) part[size_t(blockIdx.x) * 4 + k] = t;
+  }
+  if (threadIdx.x == 0) part[size_t(blockIdx.x) * 4 + 3] = 0.0;
+}
+
+// lam_i (+)= 2 f_i [g_n + g_m . sigma] psi_i   (adjoint of n = sum f psi^dag psi, m = sum f psi^dag sigma psi)
+template <typename R>
+__global__ __launch_bounds__(256) void k_density_backprop(const cpx<R>* __restrict__ psi,
+                                                          const double* __restrict__ occ,
+                                                          const double* __restrict__ gnm, int S,
+                                                          size_t N, int add, cpx<R>* __restrict__ lam) {
+  const size_t idx = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= size_t(S) * N) return;
+  const int i = int(idx / N);
+  const size_t p = idx - size_t(i) * N;
+  const double f = 2.0 * occ[i];
+  const double gn = gnm[p], gx = gnm[N + p], gy = gnm[2 * N + p], gz = gnm[3 * N + p];
+  const cpx<R> u = psi[size_t(2 * i) * N + p], d = psi[size_t(2 * i + 1) * N + p];
+  const double ux = u.x, uy = u.y, dx = d.x, dy = d.y;
+  // up' = (gn + gz) u + (gx - i gy) d ; dn' = (gx + i gy) u + (gn - gz) d
+  double ox = (gn + gz) * ux + gx * dx + gy * dy;
+  double oy = (gn + gz) * uy + gx * dy - gy * dx;
+  double px = gx * ux - gy * uy + (gn - gz) * dx;
+  double py = gx * uy + gy * ux + (gn - gz) * dy;
+  cpx<R>& lu = lam[size_t(2 * i) * N + p];
+  cpx<R>& ld = lam[size_t(2 * i + 1) * N + p];
+  if (add) {
+    ox = f * ox + double(lu.x);
+    oy = f * oy + double(lu.y);
+    px = f * px + double(ld.x);
+    py = f * py + double(ld.y);
+  } else {
+    ox *= f;
+    oy *= f;
+    px *= f;
+    py *= f;
+  }
+  lu = {R(ox), R(oy)};
+  ld = {R(px), R(py)};
+}
+
+__global__ void k_real_to_cpx(const double* __restrict__ r, size_t N, cpx<double>* __restrict__ out) {
+  const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p < N) out[p] = {r[p], 0.0};
+}
+
 // ---------------------------------------------------------------- observables row
 __global__ __launch_bounds__(256) void k_obs_row(ObsInputs in, double* __restrict__ row) {
   __shared__ double red[4];
@@ -951,6 +1083,36 @@ hipError_t launch_axpby(void* y, const void* x, size_t count, R a_re, R a_im, R 
   return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_pair(const void* mu, const void* w, int S, size_t N, double gamma, double* g,
+                       hipStream_t st) {
+  hipLaunchKernelGGL((k_pair<R>), dim3(nblocks(N, 256)), dim3(256), 0, st,
+                     reinterpret_cast<const cpx<R>*>(mu), reinterpret_cast<const cpx<R>*>(w), S, N,
+                     gamma, g);
+  return hipGetLastError();
+}
+hipError_t launch_field_adjoint(const double* rho, const double* g, const double* pg, int xc,
+                                double thr, size_t N, double* gnm, double* part, int* nblk_out,
+                                hipStream_t st) {
+  const unsigned nb = nblocks(N, 256);
+  *nblk_out = int(nb);
+  hipLaunchKernelGGL(k_field_adjoint, dim3(nb), dim3(256), 0, st, rho, g, pg, xc, thr, N, gnm, part);
+  return hipGetLastError();
+}
+template <typename R>
+hipError_t launch_density_backprop(const void* psi, const double* occ, const double* gnm, int S,
+                                   size_t N, int add, void* lam, hipStream_t st) {
+  hipLaunchKernelGGL((k_density_backprop<R>), dim3(nblocks(size_t(S) * N, 256)), dim3(256), 0, st,
+                     reinterpret_cast<const cpx<R>*>(psi), occ, gnm, S, N, add,
+                     reinterpret_cast<cpx<R>*>(lam));
+  return hipGetLastError();
+}
+hipError_t launch_real_to_cpx(const double* r, size_t N, void* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_real_to_cpx, dim3(nblocks(N, 256)), dim3(256), 0, st, r, N,
+                     reinterpret_cast<cpx<double>*>(out));
+  return hipGetLastError();
+}
+
 // explicit instantiations
 #define NCT_INST(R)                                                                                \
   template hipError_t launch_plane_stage<R>(const int*, int, const StageArgs<R>&, const ProjTables&, \
@@ -971,7 +1133,11 @@ hipError_t launch_axpby(void* y, const void* x, size_t count, R a_re, R a_im, R 
                                              hipStream_t);                                         \
   template hipError_t launch_seed<R>(const void*, const double*, int, size_t, double, double,      \
                                      double, double, void*, hipStream_t);                          \
-  template hipError_t launch_axpby<R>(void*, const void*, size_t, R, R, R, hipStream_t);
+  template hipError_t launch_axpby<R>(void*, const void*, size_t, R, R, R, hipStream_t);          \
+  template hipError_t launch_pair<R>(const void*, const void*, int, size_t, double, double*,      \
+                                     hipStream_t);                                               \
+  template hipError_t launch_density_backprop<R>(const void*, const double*, const double*, int,  \
+                                                 size_t, int, void*, hipStream_t);
 NCT_INST(double)
 NCT_INST(float)
 

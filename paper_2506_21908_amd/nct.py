@@ -274,3 +274,78 @@ def states_to_device(psi0: np.ndarray, precision: int = NCT_FP64):
 
 def version() -> str:
     return lib().nct_version().decode()
+
+
+def _pulses_with(pulses, theta):
+    import dataclasses
+    k = len(pulses)
+    out = []
+    for i, p in enumerate(pulses):
+        out.append(dataclasses.replace(p, A=float(theta[i]), omega=float(theta[k + i])))
+    return out
+
+
+def _make_pulse_mz():
+    import torch
+
+    class PulseMz(torch.autograd.Function):
+        """L = M_z(t0 + nsteps dt) = int m_z dV as a function of the pulse parameters
+        theta = (A_1..A_k, omega_1..omega_k) of the external field B_ext(t).
+
+        forward: runs the trajectory with nct_step, keeping a copy of the states every
+        checkpoint_every steps.  backward: seeds lam = 2 dV f sigma_z psi_T
+        (nct_magnetization_seed), then for each segment in reverse re-runs it with the tape on
+        (nct_step(tape=1)) and calls nct_backward_step step by step; the library adds
+        dL/dB . dB/dtheta into the gradient.  The system's tape_steps must be >= checkpoint_every.
+        """
+
+        @staticmethod
+        def forward(ctx, theta, system, psi0, pulses, nsteps, checkpoint_every, t0=0.0,
+                    B0=(0.0, 0.0, 0.0)):
+            th = theta.detach().cpu().double().numpy()
+            system.set_potentials(B0=B0, pulses=_pulses_with(pulses, th))
+            dt = float(system.params.dt)
+            psi = psi0.detach().clone()
+            ckpts = []
+            t = float(t0)
+            done = 0
+            while done < nsteps:
+                n = min(int(checkpoint_every), nsteps - done)
+                ckpts.append((psi.clone(), t, n))
+                system.step(psi, t, n)
+                t += n * dt
+                done += n
+            tot = system.density_magnetization(psi, t, totals=True)
+            ctx.system = system
+            ctx.ckpts = ckpts
+            ctx.psi_final = psi
+            ctx.npar = 2 * len(pulses)
+            return torch.tensor(float(tot[3]), dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gout):
+            s = ctx.system
+            dt = float(s.params.dt)
+            lam = torch.empty_like(ctx.psi_final)
+            s.magnetization_seed(ctx.psi_final, (0.0, 0.0, 1.0), lam)
+            grad = np.zeros(ctx.npar)
+            for psi_c, t_c, n in reversed(ctx.ckpts):
+                psi = psi_c.clone()
+                s.step(psi, t_c, n, tape=True)
+                for j in reversed(range(n)):
+                    s.backward_step(j, None, t_c + j * dt, lam, lam, grad)
+            g = torch.from_numpy(grad * float(gout))
+            return g, None, None, None, None, None, None, None
+
+    return PulseMz
+
+
+_PULSE_MZ = None
+
+
+def pulse_mz(theta, system, psi0, pulses, nsteps, checkpoint_every, t0=0.0, B0=(0.0, 0.0, 0.0)):
+    """Differentiable final M_z with respect to the pulse parameters (see PulseMz)."""
+    global _PULSE_MZ
+    if _PULSE_MZ is None:
+        _PULSE_MZ = _make_pulse_mz()
+    return _PULSE_MZ.apply(theta, system, psi0, pulses, nsteps, checkpoint_every, t0, B0)
