@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-mixed comparison run")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
+    ap.add_argument("--adjoint-segment", type=int, default=10)
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB device copy first (PMC scale reference)")
     args = ap.parse_args()
@@ -104,7 +106,10 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    def run(precision_flag, steps, warmup, timing):
+    def run(precision_flag, steps, warmup, mask, breakdown_steps=0):
+        """Timed region: exactly `steps` ETRS steps; HIP events only around the kernel classes in
+        `mask` (the plane pass).  Then, outside the timed region, `breakdown_steps` more steps with
+        every class instrumented for the per-kernel breakdown."""
         s = nct.system_from_workload(w, precision=precision_flag)
         psi = nct.states_to_device(w.psi0, precision_flag)
         t = 0.0
@@ -112,34 +117,39 @@ def main():
             s.step(psi, t, warmup)
             t += warmup * w.dt
         torch.cuda.synchronize()
-        if timing:
-            s.set_timing(True)
+        s.set_timing(mask)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s.step(psi, t, steps)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        tim = s.timing() if timing else None
+        tim = s.timing()
+        full = None
+        if breakdown_steps:
+            s.set_timing(-1)
+            s.step(psi, t + steps * w.dt, breakdown_steps)
+            full = s.timing()
         s.close()
         del psi
         torch.cuda.empty_cache()
-        return el, tim
+        return el, tim, full
 
     pflag = nct.NCT_FP64 if args.precision == "fp64" else nct.NCT_FP32_MIXED
-    el, tim = run(pflag, args.steps, args.warmup, True)
+    el, tim, full = run(pflag, args.steps, args.warmup, 1, breakdown_steps=10)
     print(f"[bench] {args.steps} steps in {el:.3f} s", file=sys.stderr, flush=True)
     value = args.steps / el
     ms_step = 1e3 * el / args.steps
 
     ms, cnt, by, fl = tim["plane_stage"]
     achieved = (by / cnt) / (ms / cnt * 1e-3) / 1e9 if cnt else 0.0
-    hp_ms = sum(tim[k][0] for k in ("plane_stage", "xpass", "proj"))
-    hp_by = sum(tim[k][2] for k in ("plane_stage", "xpass", "proj"))
-    xs = tim["xpass"]
-    pj = tim["proj"]
-    breakdown = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps,
+    nb = 10
+    hp_ms = sum(full[k][0] for k in ("plane_stage", "xpass", "proj"))
+    hp_by = sum(full[k][2] for k in ("plane_stage", "xpass", "proj"))
+    xs = full["xpass"]
+    pj = full["proj"]
+    breakdown = {k: {"ms_per_step": v[0] / nb, "launches_per_step": v[1] / nb,
                      "GBps": (v[2] / (v[0] * 1e-3) / 1e9) if v[0] > 0 else None}
-                 for k, v in tim.items() if v[1] > 0}
+                 for k, v in full.items() if v[1] > 0}
     traffic = read_traffic(args.precision)
 
     out = {
@@ -170,15 +180,47 @@ def main():
         "xpass_GBps": xs[2] / (xs[0] * 1e-3) / 1e9 if xs[0] > 0 else None,
         "projector_mfma": {"TFLOPs": (pj[3] / (pj[0] * 1e-3) / 1e12) if pj[0] > 0 else None,
                            "peak_TFLOPs": 78.6 if args.precision == "fp64" else 157.3,
-                           "ms_per_step": pj[0] / args.steps},
+                           "ms_per_step": pj[0] / nb},
         "kernel_breakdown": breakdown,
+        "kernel_breakdown_note": "separate 10-step pass with every kernel class instrumented",
     }
     if not args.no_mixed and args.precision == "fp64":
-        el2, tim2 = run(nct.NCT_FP32_MIXED, args.steps, args.warmup, True)
+        el2, tim2, _ = run(nct.NCT_FP32_MIXED, args.steps, args.warmup, 1)
         ms2, cnt2, by2, _ = tim2["plane_stage"]
         out["fp32_mixed"] = {"value": args.steps / el2, "unit": "steps/s",
                              "ms_per_step": 1e3 * el2 / args.steps,
                              "plane_stage_GBps": (by2 / (ms2 * 1e-3) / 1e9) if ms2 > 0 else None}
+    if not args.no_adjoint:
+        C = args.adjoint_segment
+        s = nct.system_from_workload(w, precision=pflag, tape_steps=C)
+        psi = nct.states_to_device(w.psi0, pflag)
+        lam = torch.empty_like(psi)
+        s.step(psi, 0.0, 2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(psi, 0.1, C)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        s.magnetization_seed(psi, (0.0, 0.0, 1.0), lam)
+        psi_c = nct.states_to_device(w.psi0, pflag)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(psi_c, 0.0, C, tape=True)
+        torch.cuda.synchronize()
+        t_tape = time.perf_counter() - t0
+        for j in reversed(range(C)):
+            s.backward_step(j, None, j * w.dt, lam, lam)
+        torch.cuda.synchronize()
+        t_bwd = time.perf_counter() - t0
+        out["adjoint"] = {"ratio": t_bwd / t_fwd, "segment_steps": C,
+                          "forward_ms_per_step": 1e3 * t_fwd / C,
+                          "taped_forward_ms_per_step": 1e3 * t_tape / C,
+                          "backward_ms_per_step_incl_taped_rerun": 1e3 * t_bwd / C,
+                          "ratio_without_rerun": (t_bwd - t_tape) / t_fwd,
+                          "definition": "(taped re-run of the segment + backward steps) / forward steps"}
+        s.close()
+        del psi, psi_c, lam
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w)

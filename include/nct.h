@@ -199,8 +199,9 @@ enum {
   NCT_K_COUNT = 8
 };
 
-/* Profiling aid.  nct_set_timing(sys, 1) resets the counters and starts recording a pair of
- * HIP events around every kernel launch the system makes (on its stream); 0 stops.
+/* Profiling aid.  nct_set_timing(sys, mask) resets the counters and, for every kernel class k
+ * with bit k of mask set, records a pair of HIP events around each launch of that class (on the
+ * system's stream); mask = 0 stops, mask = -1 records every class.
  * nct_get_timing synchronises the stream and returns for kernel class kclass the summed
  * duration in milliseconds, the number of launches, and the algorithmic bytes and flops of
  * those launches (compulsory HBM traffic and useful arithmetic of the launch's definition,

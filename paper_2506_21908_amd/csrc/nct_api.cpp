@@ -44,6 +44,9 @@ struct nct_system {
   bool fp64 = true;
   size_t cbytes = 16;   // bytes per complex element
   hipStream_t st = nullptr;
+  hipStream_t st2 = nullptr;       // projector chain, overlapped with the column pass
+  hipEvent_t ev_rows = nullptr;    // sphere rows ready (recorded on st)
+  hipEvent_t ev_proj = nullptr;    // scatter rows ready (recorded on st2)
   std::string err;
   std::vector<DevBuf> owned;
 
@@ -125,6 +128,7 @@ struct nct_system {
     double bytes, flops;
   };
   bool timing = false;
+  unsigned timing_mask = 0;  // bit k: record class k (1: only the plane pass; all ones: everything)
   std::vector<TimedLaunch> pending;
   std::vector<hipEvent_t> free_events;
   double t_ms[NCT_K_COUNT] = {0};
@@ -191,18 +195,22 @@ hipEvent_t take_event(nct_system* s) {
 
 // Runs launch(); when timing is on, brackets it with events and books bytes/flops on class k.
 template <typename F>
-hipError_t timed(nct_system* s, int k, double bytes, double flops, F&& launch) {
-  if (!s->timing) return launch();
+hipError_t timed_on(nct_system* s, hipStream_t st, int k, double bytes, double flops, F&& launch) {
+  if (!s->timing || !((s->timing_mask >> k) & 1u)) return launch();
   hipEvent_t a = take_event(s), b = take_event(s);
   if (!a || !b) return launch();
-  hipError_t e = hipEventRecord(a, s->st);
+  hipError_t e = hipEventRecord(a, st);
   if (e != hipSuccess) return e;
   e = launch();
   if (e != hipSuccess) return e;
-  e = hipEventRecord(b, s->st);
+  e = hipEventRecord(b, st);
   if (e != hipSuccess) return e;
   s->pending.push_back({k, a, b, bytes, flops});
   return hipSuccess;
+}
+template <typename F>
+hipError_t timed(nct_system* s, int k, double bytes, double flops, F&& launch) {
+  return timed_on(s, s->st, k, bytes, flops, launch);
 }
 
 // Call after the stream has been synchronised.
@@ -546,21 +554,32 @@ struct Engine {
   double proj_flops() const { return 8.0 * s->pt.PP * 2.0 * s->pt.Jtot * s->S; }
   double beta_bytes() const { return 2.0 * s->pt.Jtot * s->pt.PP * sizeof(R) * 2; }
 
-  nct_status contract(const void* W) {
+  nct_status contract(const void* W, hipStream_t st) {
     const double cpB = double(s->natoms) * s->pt.PP * s->S * 16.0;
-    return check(timed(s, NCT_K_PROJ, rowsB() + beta_bytes() + cpB * s->pt.max_kchunks, proj_flops(), [&] {
-                   return launch_proj_contract<R>(s->pt, W, s->S, s->dV, s->Cpart, s->C, s->EC, s->st); }),
+    return check(timed_on(s, st, NCT_K_PROJ, rowsB() + beta_bytes() + cpB * s->pt.max_kchunks, proj_flops(), [&] {
+                   return launch_proj_contract<R>(s->pt, W, s->S, s->dV, s->Cpart, s->C, s->EC, st); }),
                  "proj_contract");
   }
 
-  // NL projections of the sphere rows W -> Y (scatter rows) and C
+  // NL projections of the sphere rows W -> Y (scatter rows) and C.  Enqueued on the second
+  // stream after the rows are ready; join_projections() makes the main stream wait for Y.
   nct_status projections(const void* W) {
     if (s->natoms == 0) return NCT_OK;
     nct_status r;
-    if ((r = contract(W)) != NCT_OK) return r;
+    HIPCHK(s, hipEventRecord(s->ev_rows, s->st));
+    HIPCHK(s, hipStreamWaitEvent(s->st2, s->ev_rows, 0));
+    if ((r = contract(W, s->st2)) != NCT_OK) return r;
     const double ecB = double(s->natoms) * s->pt.PP * s->S * sizeof(R) * 2;
-    return check(timed(s, NCT_K_PROJ, beta_bytes() + ecB + rowsB(), proj_flops(), [&] {
-                   return launch_proj_scatter<R>(s->pt, s->EC, s->S, s->Y, s->st); }), "proj_scatter");
+    if ((r = check(timed_on(s, s->st2, NCT_K_PROJ, beta_bytes() + ecB + rowsB(), proj_flops(), [&] {
+                     return launch_proj_scatter<R>(s->pt, s->EC, s->S, s->Y, s->st2); }), "proj_scatter")) != NCT_OK)
+      return r;
+    HIPCHK(s, hipEventRecord(s->ev_proj, s->st2));
+    return NCT_OK;
+  }
+  nct_status join_projections() {
+    if (s->natoms == 0) return NCT_OK;
+    HIPCHK(s, hipStreamWaitEvent(s->st, s->ev_proj, 0));
+    return NCT_OK;
   }
 
   void bext_now(double t, R out[3]) {
@@ -611,6 +630,7 @@ struct Engine {
       const bool last = (k == K);
       if ((r = projections(cW)) != NCT_OK) return r;
       if ((r = xpass(chat, s->tmp)) != NCT_OK) return r;
+      if ((r = join_projections()) != NCT_OK) return r;
       sa.tmp_in = s->tmp;
       sa.w_in = cw;
       sa.x_base = x;
@@ -644,7 +664,7 @@ struct Engine {
                                          twx(), s->epart, &ntiles, s->st); }), "energy")) != NCT_OK)
       return r;
     if (s->natoms) {
-      if ((r = contract(s->Wpsi)) != NCT_OK) return r;
+      if ((r = contract(s->Wpsi, s->st)) != NCT_OK) return r;
     }
     ObsInputs in;
     in.field_tot = s->ftot;
@@ -794,6 +814,7 @@ struct Engine {
         return r;
       if ((r = projections(s->Wwork)) != NCT_OK) return r;
       if ((r = xpass(s->tmp, s->tmp)) != NCT_OK) return r;
+      if ((r = join_projections()) != NCT_OK) return r;
       sa.tmp_in = s->tmp;
       sa.w_in = cur;
       sa.x_base = nullptr;
@@ -907,6 +928,7 @@ struct Engine {
     if ((r = prepare(psi, s->tmp, s->Wwork)) != NCT_OK) return r;
     if ((r = projections(s->Wwork)) != NCT_OK) return r;
     if ((r = xpass(s->tmp, s->tmp)) != NCT_OK) return r;
+    if ((r = join_projections()) != NCT_OK) return r;
     StageArgs<R> sa;
     bext_now(t, sa.bext);
     sa.fields = fieldsR();
@@ -981,8 +1003,14 @@ nct_status alloc_tape(nct_system* s, nct_system::Tape& T, int cap) {
 }
 
 void free_all(nct_system* s) {
+  if (s->st2) (void)hipStreamSynchronize(s->st2);
   for (auto& b : s->owned) (void)hipFree(b.p);
   s->owned.clear();
+  if (s->ev_rows) (void)hipEventDestroy(s->ev_rows);
+  if (s->ev_proj) (void)hipEventDestroy(s->ev_proj);
+  if (s->st2) (void)hipStreamDestroy(s->st2);
+  s->ev_rows = s->ev_proj = nullptr;
+  s->st2 = nullptr;
 }
 
 nct_status create_impl(const nct_params* p, nct_system** out) {
@@ -1086,6 +1114,12 @@ nct_status create_impl(const nct_params* p, nct_system** out) {
   if ((r = dalloc(s, 4 * 8, &p0)) != NCT_OK) return bail(r);
   s->gtot = (double*)p0;
   if (p->tape_steps > 0 && (r = alloc_tape(s, s->tape, p->tape_steps)) != NCT_OK) return bail(r);
+  if (hipStreamCreateWithFlags(&s->st2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&s->ev_rows, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&s->ev_proj, hipEventDisableTiming) != hipSuccess) {
+    fail(s, NCT_ERR_HIP, "stream/event creation failed");
+    return bail(NCT_ERR_HIP);
+  }
   hipError_t e = hipMemsetAsync(s->vext, 0, N * 8, s->st);
   if (e == hipSuccess) e = hipMemsetAsync(s->fields, 0, 4 * N * 8, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
@@ -1273,6 +1307,7 @@ nct_status nct_backward_step(nct_system* s, int tape_index, const void* psi_n, d
 nct_status nct_set_timing(nct_system* s, int enable) {
   if (!s) return NCT_ERR_ARG;
   HIPCHK(s, hipStreamSynchronize(s->st));
+  HIPCHK(s, hipStreamSynchronize(s->st2));
   harvest_timing(s);
   for (int k = 0; k < NCT_K_COUNT; ++k) {
     s->t_ms[k] = 0;
@@ -1280,6 +1315,7 @@ nct_status nct_set_timing(nct_system* s, int enable) {
     s->t_bytes[k] = 0;
     s->t_flops[k] = 0;
   }
+  s->timing_mask = unsigned(enable);
   s->timing = enable != 0;
   return NCT_OK;
 }
@@ -1289,6 +1325,7 @@ nct_status nct_get_timing(nct_system* s, int k, double* ms, long long* launches,
   if (!s) return NCT_ERR_ARG;
   if (k < 0 || k >= NCT_K_COUNT) return fail(s, NCT_ERR_ARG, "kernel class out of range");
   HIPCHK(s, hipStreamSynchronize(s->st));
+  HIPCHK(s, hipStreamSynchronize(s->st2));
   harvest_timing(s);
   if (ms) *ms = s->t_ms[k];
   if (launches) *launches = s->t_count[k];

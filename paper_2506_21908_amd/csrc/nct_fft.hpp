@@ -167,22 +167,23 @@ __device__ __forceinline__ void dft(cpx<R>* x) {
 }
 
 // ---------------------------------------------------------------- radix plans
-// Radix of DIF stage s for a line of length N (0 = no such stage).
+// Radix of DIF stage s for a line of length N (0 = no such stage).  Radices stay <= 8 where a
+// two-stage plan allows it, so a butterfly's data and twiddles fit in registers together.
 __host__ __device__ constexpr int plan_radix(int N, int s) {
   switch (N) {
     case 4: return s == 0 ? 4 : 0;
     case 6: return s == 0 ? 6 : 0;
     case 8: return s == 0 ? 8 : 0;
-    case 12: return s == 0 ? 12 : 0;
-    case 16: return s == 0 ? 16 : 0;
+    case 12: return s == 0 ? 4 : (s == 1 ? 3 : 0);
+    case 16: return s == 0 ? 4 : (s == 1 ? 4 : 0);
     case 24: return s == 0 ? 8 : (s == 1 ? 3 : 0);
     case 32: return s == 0 ? 8 : (s == 1 ? 4 : 0);
-    case 36: return s == 0 ? 12 : (s == 1 ? 3 : 0);
-    case 48: return s == 0 ? 16 : (s == 1 ? 3 : 0);
+    case 36: return s == 0 ? 6 : (s == 1 ? 6 : 0);
+    case 48: return s == 0 ? 8 : (s == 1 ? 6 : 0);
     case 64: return s == 0 ? 8 : (s == 1 ? 8 : 0);
-    case 72: return s == 0 ? 12 : (s == 1 ? 6 : 0);
-    case 96: return s == 0 ? 16 : (s == 1 ? 6 : 0);
-    case 128: return s == 0 ? 16 : (s == 1 ? 8 : 0);
+    case 72: return s == 0 ? 8 : (s == 1 ? 3 : (s == 2 ? 3 : 0));
+    case 96: return s == 0 ? 8 : (s == 1 ? 12 : 0);
+    case 128: return s == 0 ? 8 : (s == 1 ? 4 : (s == 2 ? 4 : 0));
     default: return 0;
   }
 }
@@ -217,18 +218,22 @@ __device__ __forceinline__ void lds_stage(cpx<R>* lds, const cpx<R>* tw, int tid
     cpx<R> x[RAD];
 #pragma unroll
     for (int q = 0; q < RAD; ++q) x[q] = base[q * M * ES];
-    if constexpr (FWD) {
-      dft<R, -1, RAD>(x);
-      if constexpr (M > 1) {
+    if constexpr (M > 1) {
+      // all twiddle reads issued together with the data reads
+      cpx<R> w[RAD - 1];
 #pragma unroll
-        for (int p = 1; p < RAD; ++p) x[p] = cmul(x[p], tw[b * p * TWS]);
+      for (int p = 1; p < RAD; ++p) w[p - 1] = tw[b * p * TWS];
+      if constexpr (FWD) {
+        dft<R, -1, RAD>(x);
+#pragma unroll
+        for (int p = 1; p < RAD; ++p) x[p] = cmul(x[p], w[p - 1]);
+      } else {
+#pragma unroll
+        for (int p = 1; p < RAD; ++p) x[p] = cmulc(x[p], w[p - 1]);
+        dft<R, +1, RAD>(x);
       }
     } else {
-      if constexpr (M > 1) {
-#pragma unroll
-        for (int p = 1; p < RAD; ++p) x[p] = cmulc(x[p], tw[b * p * TWS]);
-      }
-      dft<R, +1, RAD>(x);
+      dft<R, FWD ? -1 : +1, RAD>(x);
     }
 #pragma unroll
     for (int q = 0; q < RAD; ++q) base[q * M * ES] = x[q];
@@ -239,7 +244,7 @@ __device__ __forceinline__ void lds_stage(cpx<R>* lds, const cpx<R>* tw, int tid
 template <typename R, int N, int NLINES, int LS, int ES, bool FWD>
 __device__ __forceinline__ void lds_fft(cpx<R>* lds, const cpx<R>* tw, int tid, int nt) {
   constexpr int NS = plan_nstages(N);
-  static_assert(NS >= 1 && NS <= 2, "line length not supported");
+  static_assert(NS >= 1 && NS <= 3, "line length not supported");
   if constexpr (FWD) {
     lds_stage<R, N, 0, NLINES, LS, ES, true>(lds, tw, tid, nt);
     __syncthreads();
@@ -247,7 +252,15 @@ __device__ __forceinline__ void lds_fft(cpx<R>* lds, const cpx<R>* tw, int tid, 
       lds_stage<R, N, 1, NLINES, LS, ES, true>(lds, tw, tid, nt);
       __syncthreads();
     }
+    if constexpr (NS > 2) {
+      lds_stage<R, N, 2, NLINES, LS, ES, true>(lds, tw, tid, nt);
+      __syncthreads();
+    }
   } else {
+    if constexpr (NS > 2) {
+      lds_stage<R, N, 2, NLINES, LS, ES, false>(lds, tw, tid, nt);
+      __syncthreads();
+    }
     if constexpr (NS > 1) {
       lds_stage<R, N, 1, NLINES, LS, ES, false>(lds, tw, tid, nt);
       __syncthreads();

@@ -197,6 +197,183 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a
   }
 }
 
+// ---------------------------------------------------------------- plane pass, two halves
+// Same stage as k_plane_stage, with the two spinor components of the (state, x-plane) held as
+// two LDS planes and transformed concurrently by the two halves of the workgroup; the pointwise
+// 2x2 update then reads both planes.  Used when two planes fit in LDS.
+__host__ __device__ constexpr int plane2_nth(int np) { return plane_nt(np) > 512 ? 512 : plane_nt(np); }
+template <int NY, int NZ>
+constexpr size_t plane2_lds_bytes(size_t elem) {
+  return (size_t(2) * NY * (NZ + 1) + NY + NZ) * elem;
+}
+template <typename R, int NY, int NZ>
+constexpr bool plane2_fits() {
+  return plane2_lds_bytes<NY, NZ>(sizeof(cpx<R>)) <= 160 * 1024 - 1024;
+}
+
+template <typename R, int NY, int NZ>
+__global__ __launch_bounds__(2 * plane2_nth(NY* NZ)) void k_plane_stage2(StageArgs<R> a, ProjTables pt,
+                                                                          const cpx<R>* __restrict__ twy_g,
+                                                                          const cpx<R>* __restrict__ twz_g,
+                                                                          int S, int NX) {
+  constexpr int NP = NY * NZ;
+  constexpr int NTH = plane2_nth(NP);
+  constexpr int NT = 2 * NTH;
+  constexpr int PZ = NZ + 1;
+  constexpr int PL = NY * PZ;
+  constexpr int PPH = (NP + NTH - 1) / NTH;
+  constexpr int PPT = (NP + NT - 1) / NT;
+  constexpr int G = sizeof(R) == 8 ? 3 : 5;  // pointwise points per load batch
+  extern __shared__ double4 smem_d4[];
+  cpx<R>* planes = reinterpret_cast<cpx<R>*>(smem_d4);
+  cpx<R>* twy = planes + 2 * PL;
+  cpx<R>* twz = twy + NY;
+  const int tid = threadIdx.x;
+  const int h = tid / NTH;
+  const int th = tid - h * NTH;
+  const int L = xcd_logical(blockIdx.x, gridDim.x);
+  const int x = L / S;
+  const int i = L - x * S;
+  for (int k = tid; k < NY; k += NT) twy[k] = twy_g[k];
+  for (int k = tid; k < NZ; k += NT) twz[k] = twz_g[k];
+  const size_t N = size_t(NX) * NP;
+  const size_t off0 = (size_t(2 * i) * NX + x) * NP;
+  const size_t off1 = (size_t(2 * i + 1) * NX + x) * NP;
+  const size_t offh = h ? off1 : off0;
+  cpx<R>* pl = planes + h * PL;
+
+  // 1) kinetic part: each half loads and inverse-transforms its spinor's plane
+  {
+    const cpx<R>* __restrict__ tin = reinterpret_cast<const cpx<R>*>(a.tmp_in);
+    cpx<R> v[PPH];
+#pragma unroll
+    for (int j = 0; j < PPH; ++j) v[j] = tin[offh + min(th + j * NTH, NP - 1)];
+#pragma unroll
+    for (int j = 0; j < PPH; ++j) {
+      const int e = th + j * NTH;
+      if (e < NP) pl[(e / NZ) * PZ + (e % NZ)] = v[j];
+    }
+  }
+  __syncthreads();
+  plane_fft_inv<R, NY, NZ, PZ>(pl, twy, twz, th, NTH);
+
+  // 2) 2x2 local potential and Taylor update over the whole plane (both spinors per point)
+  {
+    const cpx<R>* __restrict__ win = reinterpret_cast<const cpx<R>*>(a.w_in);
+    const cpx<R>* __restrict__ xb = reinterpret_cast<const cpx<R>*>(a.x_base);
+    const bool xsep = xb && (a.x_base != a.w_in);
+    const R* __restrict__ F = a.fields;
+#pragma unroll
+    for (int j0 = 0; j0 < PPT; j0 += G) {
+      cpx<R> wu[G], wd[G], xu[G], xd[G];
+      R fv[G], fx[G], fy[G], fz[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if (j0 + g < PPT) {
+          const int e = min(tid + (j0 + g) * NT, NP - 1);  // clamped: loads unconditional
+          const size_t p = size_t(x) * NP + e;
+          wu[g] = win[off0 + e];
+          wd[g] = win[off1 + e];
+          if (xsep) {
+            xu[g] = xb[off0 + e];
+            xd[g] = xb[off1 + e];
+          } else {
+            xu[g] = wu[g];
+            xd[g] = wd[g];
+          }
+          fv[g] = F[p];
+          fx[g] = F[N + p];
+          fy[g] = F[2 * N + p];
+          fz[g] = F[3 * N + p];
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int e = tid + (j0 + g) * NT;
+        if (j0 + g < PPT && e < NP) {
+          const int q = (e / NZ) * PZ + (e % NZ);
+          const cpx<R> tu = planes[q], td = planes[PL + q];
+          const R v = fv[g], bx = fx[g] + a.bext[0], by = fy[g] + a.bext[1], bz = fz[g] + a.bext[2];
+          cpx<R> hu, hd;
+          hu.x = tu.x + (v + bz) * wu[g].x + bx * wd[g].x + by * wd[g].y;
+          hu.y = tu.y + (v + bz) * wu[g].y + bx * wd[g].y - by * wd[g].x;
+          hd.x = td.x + bx * wu[g].x - by * wu[g].y + (v - bz) * wd[g].x;
+          hd.y = td.y + bx * wu[g].y + by * wu[g].x + (v - bz) * wd[g].y;
+          cpx<R> ou = {a.cre * hu.x - a.cim * hu.y, a.cre * hu.y + a.cim * hu.x};
+          cpx<R> od = {a.cre * hd.x - a.cim * hd.y, a.cre * hd.y + a.cim * hd.x};
+          if (xb) {
+            ou.x += a.alpha * xu[g].x;
+            ou.y += a.alpha * xu[g].y;
+            od.x += a.alpha * xd[g].x;
+            od.y += a.alpha * xd[g].y;
+          }
+          planes[q] = ou;
+          planes[PL + q] = od;
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // 3) projector rows, outputs, forward transform; each half its own spinor
+  const cpx<R>* __restrict__ Y = reinterpret_cast<const cpx<R>*>(a.Y);
+  cpx<R>* __restrict__ Wr = reinterpret_cast<cpx<R>*>(a.W);
+  cpx<R>* __restrict__ wout = reinterpret_cast<cpx<R>*>(a.w_out);
+  cpx<R>* __restrict__ acc = reinterpret_cast<cpx<R>*>(a.acc);
+  cpx<R>* __restrict__ tout = reinterpret_cast<cpx<R>*>(a.tmp_out);
+  const int r0 = pt.pr_off ? pt.pr_off[x] : 0;
+  const int r1 = pt.pr_off ? pt.pr_off[x + 1] : 0;
+  const size_t rowbase = size_t(2 * i + h) * pt.Jtot;
+  if (Y) {
+    for (int r = r0; r < r1; ++r) {
+      const int jb = pt.pr_begin[r], je = pt.pr_end[r];
+      for (int J = jb + th; J < je; J += NTH) {
+        const int e = pt.pidx[J];
+        const cpx<R> y = Y[rowbase + J];
+        cpx<R>& d = pl[(e / NZ) * PZ + (e % NZ)];
+        d.x += a.cre * y.x - a.cim * y.y;
+        d.y += a.cre * y.y + a.cim * y.x;
+      }
+      __syncthreads();
+    }
+  }
+  if (Wr) {
+    for (int r = r0; r < r1; ++r) {
+      const int jb = pt.pr_begin[r], je = pt.pr_end[r];
+      for (int J = jb + th; J < je; J += NTH) {
+        const int e = pt.pidx[J];
+        Wr[rowbase + J] = pl[(e / NZ) * PZ + (e % NZ)];
+      }
+    }
+  }
+  if (acc) {
+    cpx<R> v[PPH];
+#pragma unroll
+    for (int j = 0; j < PPH; ++j) v[j] = acc[offh + min(th + j * NTH, NP - 1)];
+#pragma unroll
+    for (int j = 0; j < PPH; ++j) {
+      const int e = th + j * NTH;
+      if (e < NP) acc[offh + e] = v[j] + pl[(e / NZ) * PZ + (e % NZ)];
+    }
+  }
+  if (wout) {
+#pragma unroll
+    for (int j = 0; j < PPH; ++j) {
+      const int e = th + j * NTH;
+      if (e < NP) wout[offh + e] = pl[(e / NZ) * PZ + (e % NZ)];
+    }
+  }
+  if (tout) {
+    __syncthreads();
+    plane_fft_fwd<R, NY, NZ, PZ>(pl, twy, twz, th, NTH);
+#pragma unroll
+    for (int j = 0; j < PPH; ++j) {
+      const int e = th + j * NTH;
+      if (e < NP) tout[offh + e] = pl[(e / NZ) * PZ + (e % NZ)];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- plane pass: transform only
 template <typename R, int NY, int NZ>
 __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_fwd(const cpx<R>* in, cpx<R>* out,
@@ -285,25 +462,39 @@ __global__ __launch_bounds__(XP_NT) void k_xpass(const cpx<R>* src, cpx<R>* dst,
   const int q0 = tl * TC;
   for (int k = tid; k < NX; k += XP_NT) tw[k] = twx_g[k];
   const size_t base = size_t(b) * NX * NYZ + q0;
-  for (int e = tid; e < NX * TC; e += XP_NT) {
-    const int xx = e / TC, c = e - (e / TC) * TC;
-    tile[e] = src[base + size_t(xx) * NYZ + c];
+  constexpr int PER = (NX * TC + XP_NT - 1) / XP_NT;
+  {
+    cpx<R> v[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int e = min(tid + j * XP_NT, NX * TC - 1);  // clamped: every load unconditional
+      v[j] = src[base + size_t(e / TC) * NYZ + (e % TC)];
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int e = tid + j * XP_NT;
+      if (e < NX * TC) tile[e] = v[j];
+    }
   }
   __syncthreads();
   lds_fft<R, NX, TC, 1, TC, true>(tile, tw, tid, XP_NT);
-  for (int e = tid; e < NX * TC; e += XP_NT) {
-    const int xx = e / TC, c = e - (e / TC) * TC;
-    const R g = g2x[xx] + g2yz[q0 + c];
-    R m;
-    if (mode == 0) m = kscale * g;
-    else m = g > R(0) ? kscale / g : R(0);
-    tile[e] = cscale(tile[e], m);
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int e = tid + j * XP_NT;
+    if (e < NX * TC) {
+      const R g = g2x[e / TC] + g2yz[q0 + (e % TC)];
+      R m;
+      if (mode == 0) m = kscale * g;
+      else m = g > R(0) ? kscale / g : R(0);
+      tile[e] = cscale(tile[e], m);
+    }
   }
   __syncthreads();
   lds_fft<R, NX, TC, 1, TC, false>(tile, tw, tid, XP_NT);
-  for (int e = tid; e < NX * TC; e += XP_NT) {
-    const int xx = e / TC, c = e - (e / TC) * TC;
-    dst[base + size_t(xx) * NYZ + c] = tile[e];
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int e = tid + j * XP_NT;
+    if (e < NX * TC) dst[base + size_t(e / TC) * NYZ + (e % TC)] = tile[e];
   }
 }
 
@@ -323,9 +514,19 @@ __global__ __launch_bounds__(XP_NT) void k_xpass_energy(const cpx<R>* src, int N
   const int q0 = tl * TC;
   for (int k = tid; k < NX; k += XP_NT) tw[k] = twx_g[k];
   const size_t base = size_t(b) * NX * NYZ + q0;
-  for (int e = tid; e < NX * TC; e += XP_NT) {
-    const int xx = e / TC, c = e - (e / TC) * TC;
-    tile[e] = src[base + size_t(xx) * NYZ + c];
+  constexpr int PER = (NX * TC + XP_NT - 1) / XP_NT;
+  {
+    cpx<R> v[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int e = min(tid + j * XP_NT, NX * TC - 1);  // clamped: every load unconditional
+      v[j] = src[base + size_t(e / TC) * NYZ + (e % TC)];
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int e = tid + j * XP_NT;
+      if (e < NX * TC) tile[e] = v[j];
+    }
   }
   __syncthreads();
   lds_fft<R, NX, TC, 1, TC, true>(tile, tw, tid, XP_NT);
@@ -495,66 +696,72 @@ struct mfma16<float> {
 };
 
 constexpr int KC = 64;  // contraction K chunk per wave
+constexpr int KU = 4;   // k-steps whose operands are loaded together
 
 // Cpart[a][kc][p][i] = sum_{k in chunk} conj(beta[a][k][p]) W[i][k], k = 2 (J - off_a) + s.
-// One wave: two 16x16 output tiles (p < 32) of 16 states; A/B operands as
+// One wave: PP/16 output tiles of 16 projectors x 16 states; A/B operands as
 // A[row = lane%16][k = lane/16], B[k = lane/16][col = lane%16]; D rows from mfma16::row.
-template <typename R>
+template <typename R, int PP>
 __global__ __launch_bounds__(64) void k_proj_contract(ProjTables pt, const cpx<R>* __restrict__ W,
                                                       int S, cpx<double>* __restrict__ Cpart) {
   using M = mfma16<R>;
+  constexpr int NMT = PP / 16;
   const int a = blockIdx.x, nt = blockIdx.y, kc = blockIdx.z;
   const int off = pt.row_off[a];
   const int K = 2 * (pt.row_off[a + 1] - off);
-  if (kc * KC >= K) return;
+  const int nch_a = (K + KC - 1) / KC;
+  if (kc >= nch_a) return;
   const int lane = threadIdx.x;
   const int col = lane & 15, kl = lane >> 4;
   const int i = nt * 16 + col;
   const cpx<R>* __restrict__ beta = reinterpret_cast<const cpx<R>*>(pt.beta);
-  const int nmt = pt.PP / 16;
-  typename M::acc ar[2], ai[2];
-  ar[0] = M::zero(); ar[1] = M::zero(); ai[0] = M::zero(); ai[1] = M::zero();
+  typename M::acc ar[NMT], ai[NMT];
+#pragma unroll
+  for (int mt = 0; mt < NMT; ++mt) {
+    ar[mt] = M::zero();
+    ai[mt] = M::zero();
+  }
   const int kend = min(K, kc * KC + KC);
-  for (int k0 = kc * KC; k0 < kend; k0 += 4) {
-    const int k = k0 + kl;
-    R br = 0, bi = 0;
-    if (k < K && i < S) {
-      const int J = off + (k >> 1), s = k & 1;
-      const cpx<R> w = W[size_t(2 * i + s) * pt.Jtot + J];
-      br = w.x;
-      bi = w.y;
+  for (int k0 = kc * KC; k0 < kend; k0 += 4 * KU) {
+    cpx<R> bw[KU], bb[KU][NMT];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int k = k0 + 4 * u + kl;
+      const bool ok = k < kend;
+      const int kk = ok ? k : kc * KC;  // clamped index, value zeroed below
+      const int J = off + (kk >> 1), s = kk & 1;
+      const cpx<R> w = W[size_t(2 * min(i, S - 1) + s) * pt.Jtot + J];
+      bw[u] = (ok && i < S) ? w : cpx<R>{R(0), R(0)};
+#pragma unroll
+      for (int mt = 0; mt < NMT; ++mt) {
+        const cpx<R> v = beta[(size_t(2 * off) + kk) * PP + mt * 16 + col];
+        bb[u][mt] = ok ? v : cpx<R>{R(0), R(0)};
+      }
     }
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-      if (mt < nmt) {
-        const int p = mt * 16 + col;
-        R xr = 0, xi = 0;
-        if (k < K) {
-          const cpx<R> bb = beta[(size_t(2 * off) + k) * pt.PP + p];
-          xr = bb.x;
-          xi = bb.y;
-        }
-        ar[mt] = M::op(xr, br, ar[mt]);
-        ar[mt] = M::op(xi, bi, ar[mt]);
-        ai[mt] = M::op(xr, bi, ai[mt]);
-        ai[mt] = M::op(-xi, br, ai[mt]);
+    for (int u = 0; u < KU; ++u) {
+#pragma unroll
+      for (int mt = 0; mt < NMT; ++mt) {
+        ar[mt] = M::op(bb[u][mt].x, bw[u].x, ar[mt]);
+        ar[mt] = M::op(bb[u][mt].y, bw[u].y, ar[mt]);
+        ai[mt] = M::op(bb[u][mt].x, bw[u].y, ai[mt]);
+        ai[mt] = M::op(-bb[u][mt].y, bw[u].x, ai[mt]);
       }
     }
   }
   const int nch = pt.max_kchunks;
 #pragma unroll
-  for (int mt = 0; mt < 2; ++mt) {
-    if (mt >= nmt) break;
+  for (int mt = 0; mt < NMT; ++mt) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int p = mt * 16 + M::row(r, kl);
       if (i < S)
-        Cpart[((size_t(a) * nch + kc) * pt.PP + p) * S + i] = {double(ar[mt][r]), double(ai[mt][r])};
+        Cpart[((size_t(a) * nch + kc) * PP + p) * S + i] = {double(ar[mt][r]), double(ai[mt][r])};
     }
   }
 }
 
-// C[a][p][i] = dV sum_kc Cpart; EC = E[a][p] C (R precision)
+// C[a][p][i] = dV sum_kc Cpart (chunk order); EC = E[a][p] C (R precision)
 template <typename R>
 __global__ __launch_bounds__(256) void k_proj_reduce(ProjTables pt, const cpx<double>* __restrict__ Cpart,
                                                      int S, double dV, cpx<double>* __restrict__ C,
@@ -567,9 +774,22 @@ __global__ __launch_bounds__(256) void k_proj_reduce(ProjTables pt, const cpx<do
   const int a = int(idx / (size_t(S) * pt.PP));
   const int K = 2 * (pt.row_off[a + 1] - pt.row_off[a]);
   const int nch_a = (K + KC - 1) / KC;
+  const size_t stride = size_t(pt.PP) * S;
+  const cpx<double>* src = Cpart + (size_t(a) * pt.max_kchunks * pt.PP + p) * S + i;
   double sr = 0, si = 0;
-  for (int kc = 0; kc < nch_a; ++kc) {
-    const cpx<double> v = Cpart[((size_t(a) * pt.max_kchunks + kc) * pt.PP + p) * S + i];
+  int kc = 0;
+  for (; kc + 8 <= nch_a; kc += 8) {
+    cpx<double> v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = src[size_t(kc + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      sr += v[u].x;
+      si += v[u].y;
+    }
+  }
+  for (; kc < nch_a; ++kc) {
+    const cpx<double> v = src[size_t(kc) * stride];
     sr += v.x;
     si += v.y;
   }
@@ -581,10 +801,11 @@ __global__ __launch_bounds__(256) void k_proj_reduce(ProjTables pt, const cpx<do
 }
 
 // Y[i][s][J] = sum_p beta[J][s][p] EC[a][p][i]; rows k = 2 (J - off_a) + s
-template <typename R>
+template <typename R, int PP>
 __global__ __launch_bounds__(64) void k_proj_scatter(ProjTables pt, const cpx<R>* __restrict__ EC,
                                                      int S, cpx<R>* __restrict__ Y) {
   using M = mfma16<R>;
+  constexpr int KS = PP / 4;
   const int a = blockIdx.x, rt = blockIdx.y, nt = blockIdx.z;
   const int off = pt.row_off[a];
   const int K2 = 2 * (pt.row_off[a + 1] - off);
@@ -594,24 +815,22 @@ __global__ __launch_bounds__(64) void k_proj_scatter(ProjTables pt, const cpx<R>
   const int row = rt * 16 + col;
   const int i = nt * 16 + col;
   const cpx<R>* __restrict__ beta = reinterpret_cast<const cpx<R>*>(pt.beta);
+  cpx<R> xb[KS], ec[KS];
+#pragma unroll
+  for (int u = 0; u < KS; ++u) {
+    const int p = 4 * u + kl;
+    const cpx<R> bv = beta[(size_t(2 * off) + min(row, K2 - 1)) * PP + p];
+    xb[u] = row < K2 ? bv : cpx<R>{R(0), R(0)};
+    const cpx<R> ev = EC[(size_t(a) * PP + p) * S + min(i, S - 1)];
+    ec[u] = i < S ? ev : cpx<R>{R(0), R(0)};
+  }
   typename M::acc yr = M::zero(), yi = M::zero();
-  for (int k0 = 0; k0 < pt.PP; k0 += 4) {
-    const int p = k0 + kl;
-    R xr = 0, xi = 0, er = 0, ei = 0;
-    if (row < K2) {
-      const cpx<R> bb = beta[(size_t(2 * off) + row) * pt.PP + p];
-      xr = bb.x;
-      xi = bb.y;
-    }
-    if (i < S) {
-      const cpx<R> ec = EC[(size_t(a) * pt.PP + p) * S + i];
-      er = ec.x;
-      ei = ec.y;
-    }
-    yr = M::op(xr, er, yr);
-    yr = M::op(-xi, ei, yr);
-    yi = M::op(xr, ei, yi);
-    yi = M::op(xi, er, yi);
+#pragma unroll
+  for (int u = 0; u < KS; ++u) {
+    yr = M::op(xb[u].x, ec[u].x, yr);
+    yr = M::op(-xb[u].y, ec[u].y, yr);
+    yi = M::op(xb[u].x, ec[u].y, yi);
+    yi = M::op(xb[u].y, ec[u].x, yi);
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
@@ -880,6 +1099,16 @@ hipError_t launch_plane_stage(const int n[3], int S, const StageArgs<R>& a, cons
   const unsigned grid = unsigned(S) * unsigned(n[0]);
 #define X(A, B)                                                                             \
   if (n[1] == A && n[2] == B) {                                                             \
+    if constexpr (plane2_fits<R, A, B>()) {                                                 \
+      constexpr size_t lds2 = plane2_lds_bytes<A, B>(sizeof(cpx<R>));                       \
+      auto kern2 = k_plane_stage2<R, A, B>;                                                 \
+      hipError_t e2 = set_lds(kern2, lds2);                                                 \
+      if (e2 != hipSuccess) return e2;                                                      \
+      hipLaunchKernelGGL(kern2, dim3(grid), dim3(2 * plane2_nth(A * B)), lds2, st, a, pt,   \
+                         reinterpret_cast<const cpx<R>*>(twy), reinterpret_cast<const cpx<R>*>(twz), \
+                         S, n[0]);                                                          \
+      return hipGetLastError();                                                             \
+    }                                                                                       \
     constexpr size_t lds = plane_lds_bytes<A, B>(sizeof(cpx<R>));                           \
     auto kern = k_plane_stage<R, A, B>;                                                     \
     hipError_t e = set_lds(kern, lds);                                                      \
@@ -1039,9 +1268,13 @@ hipError_t launch_proj_contract(const ProjTables& pt, const void* W, int S, doub
                                 void* Cpart, void* C, void* EC, hipStream_t st) {
   if (pt.natoms == 0) return hipSuccess;
   const unsigned ntile = unsigned((S + 15) / 16);
-  hipLaunchKernelGGL((k_proj_contract<R>), dim3(pt.natoms, ntile, pt.max_kchunks), dim3(64), 0, st,
-                     pt, reinterpret_cast<const cpx<R>*>(W), S,
-                     reinterpret_cast<cpx<double>*>(Cpart));
+  const dim3 grid(pt.natoms, ntile, pt.max_kchunks);
+  if (pt.PP == 16)
+    hipLaunchKernelGGL((k_proj_contract<R, 16>), grid, dim3(64), 0, st, pt,
+                       reinterpret_cast<const cpx<R>*>(W), S, reinterpret_cast<cpx<double>*>(Cpart));
+  else
+    hipLaunchKernelGGL((k_proj_contract<R, 32>), grid, dim3(64), 0, st, pt,
+                       reinterpret_cast<const cpx<R>*>(W), S, reinterpret_cast<cpx<double>*>(Cpart));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t total = size_t(pt.natoms) * pt.PP * S;
@@ -1056,8 +1289,13 @@ hipError_t launch_proj_scatter(const ProjTables& pt, const void* EC, int S, void
                                hipStream_t st) {
   if (pt.natoms == 0) return hipSuccess;
   const unsigned ntile = unsigned((S + 15) / 16);
-  hipLaunchKernelGGL((k_proj_scatter<R>), dim3(pt.natoms, pt.max_rowtiles, ntile), dim3(64), 0, st,
-                     pt, reinterpret_cast<const cpx<R>*>(EC), S, reinterpret_cast<cpx<R>*>(Y));
+  const dim3 grid(pt.natoms, pt.max_rowtiles, ntile);
+  if (pt.PP == 16)
+    hipLaunchKernelGGL((k_proj_scatter<R, 16>), grid, dim3(64), 0, st, pt,
+                       reinterpret_cast<const cpx<R>*>(EC), S, reinterpret_cast<cpx<R>*>(Y));
+  else
+    hipLaunchKernelGGL((k_proj_scatter<R, 32>), grid, dim3(64), 0, st, pt,
+                       reinterpret_cast<const cpx<R>*>(EC), S, reinterpret_cast<cpx<R>*>(Y));
   return hipGetLastError();
 }
 

@@ -235,8 +235,9 @@ class System:
                                             _dptr(dLdtheta) if dLdtheta is not None else None))
         return dLdB
 
-    def set_timing(self, enable: bool):
-        self._check(lib().nct_set_timing(self.h, int(enable)))
+    def set_timing(self, mask: int):
+        """Bit k of mask instruments kernel class k (KERNEL_CLASSES); -1 = all, 0 = off."""
+        self._check(lib().nct_set_timing(self.h, int(mask)))
 
     def timing(self):
         """{class: (ms, launches, algorithmic bytes, flops)} since the last set_timing."""
