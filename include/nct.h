@@ -115,6 +115,9 @@ typedef struct {
   int taylor_order;           /* 1..16 */
   int precision;              /* NCT_FP64 or NCT_FP32_MIXED */
   int tape_steps;             /* steps the adjoint tape can hold (0: recompute mode only) */
+  int overlap;                /* nonzero: run the Taylor stages of two halves of the states on two
+                                 internal streams so their passes overlap (off by default: the
+                                 per-kernel timings then measure overlapping kernels) */
   void *stream;               /* hipStream_t or NULL */
 } nct_params;
 

@@ -47,6 +47,15 @@ struct nct_system {
   hipStream_t st2 = nullptr;       // projector chain, overlapped with the column pass
   hipEvent_t ev_rows = nullptr;    // sphere rows ready (recorded on st)
   hipEvent_t ev_proj = nullptr;    // scatter rows ready (recorded on st2)
+  // second state group: its Taylor stages run on their own streams, overlapping the first
+  // group's (states are contiguous in the state-major layout, so a group is a sub-array)
+  int ngroups = 1;
+  int S0 = 0;                      // states of group 0 (group 1: S - S0)
+  hipStream_t stB = nullptr, stB2 = nullptr;
+  hipEvent_t evB_rows = nullptr, evB_proj = nullptr, ev_fork = nullptr, ev_join = nullptr;
+  void* CpartB = nullptr;
+  void* CB = nullptr;
+  void* ECB = nullptr;
   std::string err;
   std::vector<DevBuf> owned;
 
@@ -613,6 +622,94 @@ struct Engine {
                  "plane_stage");
   }
 
+  // ---- state groups
+  struct Group {
+    int i0, S;
+    hipStream_t st, st2;
+    hipEvent_t ev_rows, ev_proj;
+    void *Cpart, *C, *EC;
+  };
+  int groups(Group* g) const {
+    g[0] = {0, s->ngroups > 1 ? s->S0 : s->S, s->st, s->st2, s->ev_rows, s->ev_proj, s->Cpart, s->C, s->EC};
+    if (s->ngroups == 1) return 1;
+    g[1] = {s->S0, s->S - s->S0, s->stB, s->stB2, s->evB_rows, s->evB_proj, s->CpartB, s->CB, s->ECB};
+    return 2;
+  }
+  template <typename P>
+  P* offs(P* p, int i0) const {  // states
+    return p ? reinterpret_cast<P*>(const_cast<char*>(reinterpret_cast<const char*>(p)) +
+                                    size_t(i0) * 2 * s->N * sizeof(R) * 2)
+             : nullptr;
+  }
+  template <typename P>
+  P* offr(P* p, int i0) const {  // sphere rows
+    return p ? reinterpret_cast<P*>(const_cast<char*>(reinterpret_cast<const char*>(p)) +
+                                    size_t(i0) * 2 * s->pt.Jtot * sizeof(R) * 2)
+             : nullptr;
+  }
+  nct_status fork_groups() {
+    if (s->ngroups == 1) return NCT_OK;
+    HIPCHK(s, hipEventRecord(s->ev_fork, s->st));
+    HIPCHK(s, hipStreamWaitEvent(s->stB, s->ev_fork, 0));
+    return NCT_OK;
+  }
+  nct_status join_groups() {
+    if (s->ngroups == 1) return NCT_OK;
+    HIPCHK(s, hipEventRecord(s->ev_join, s->stB));
+    HIPCHK(s, hipStreamWaitEvent(s->st, s->ev_join, 0));
+    return NCT_OK;
+  }
+
+  // One H application of a state group: projector chain of rows cW (second stream, joined
+  // before the plane pass), column pass of chat into tmp, fused plane pass described by sa
+  // (full-size pointers; offset here to the group).
+  nct_status stage_group(const Group& g, const void* cW, const void* chat, const StageArgs<R>& sa_full) {
+    nct_status r;
+    const double frac = double(g.S) / double(s->S);
+    if (s->natoms) {
+      HIPCHK(s, hipEventRecord(g.ev_rows, g.st));
+      HIPCHK(s, hipStreamWaitEvent(g.st2, g.ev_rows, 0));
+      const double cpB = double(s->natoms) * s->pt.PP * g.S * 16.0;
+      if ((r = check(timed_on(s, g.st2, NCT_K_PROJ, frac * (rowsB() + beta_bytes()) + cpB * s->pt.max_kchunks,
+                              frac * proj_flops(), [&] {
+                                return launch_proj_contract<R>(s->pt, offr(cW, g.i0), g.S, s->dV, g.Cpart, g.C,
+                                                               g.EC, g.st2); }), "proj_contract")) != NCT_OK)
+        return r;
+      const double ecB = double(s->natoms) * s->pt.PP * g.S * sizeof(R) * 2;
+      if ((r = check(timed_on(s, g.st2, NCT_K_PROJ, beta_bytes() + ecB + frac * rowsB(), frac * proj_flops(), [&] {
+                       return launch_proj_scatter<R>(s->pt, g.EC, g.S, offr(s->Y, g.i0), g.st2); }),
+                     "proj_scatter")) != NCT_OK)
+        return r;
+      HIPCHK(s, hipEventRecord(g.ev_proj, g.st2));
+    }
+    if ((r = check(timed_on(s, g.st, NCT_K_XPASS, 2 * psiB() * frac, 0, [&] {
+           return launch_xpass<R>(s->n, 2 * g.S, offs(chat, g.i0), offs(s->tmp, g.i0), g2x(), g2yz(),
+                                  R(0.5 / double(s->N)), 0, twx(), g.st); }), "xpass")) != NCT_OK)
+      return r;
+    if (s->natoms) HIPCHK(s, hipStreamWaitEvent(g.st, g.ev_proj, 0));
+    StageArgs<R> sa = sa_full;
+    sa.tmp_in = offs(sa.tmp_in, g.i0);
+    sa.tmp_out = offs(sa.tmp_out, g.i0);
+    sa.w_in = offs(sa.w_in, g.i0);
+    sa.x_base = offs(sa.x_base, g.i0);
+    sa.w_out = offs(sa.w_out, g.i0);
+    sa.acc = offs(sa.acc, g.i0);
+    sa.Y = s->natoms ? offr(s->Y, g.i0) : nullptr;
+    sa.W = offr(sa.W, g.i0);
+    double b = psiB();
+    if (sa.w_in) b += psiB();
+    if (sa.x_base && sa.x_base != sa.w_in) b += psiB();
+    if (sa.Y) b += rowsB();
+    if (sa.w_out) b += psiB();
+    if (sa.tmp_out) b += psiB();
+    if (sa.W) b += rowsB();
+    if (sa.acc) b += 2 * psiB();
+    b = b * frac + 4.0 * s->N * sizeof(R);
+    return check(timed_on(s, g.st, NCT_K_PLANE_STAGE, b, 0, [&] {
+                   return launch_plane_stage<R>(s->n, g.S, sa, s->pt, twy(), twz(), g.st); }),
+                 "plane_stage");
+  }
+
   // T_K(-i a H) x by Horner stages w_k = x + (-i a/(K-k+1)) H w_{k-1}, w_0 = x.
   // stage_out[k-1] (k = 1..K-1), if given, receives w_k (the adjoint tape); else the work buffer.
   nct_status taylor(const void* x, const void* xhat, const void* xW, void* out, void* outhat,
@@ -626,28 +723,28 @@ struct Engine {
     bext_now(t, sa.bext);
     sa.fields = fieldsR();
     nct_status r;
+    Group G[2];
+    const int ng = groups(G);
+    if ((r = fork_groups()) != NCT_OK) return r;
     for (int k = 1; k <= K; ++k) {
       const bool last = (k == K);
-      if ((r = projections(cW)) != NCT_OK) return r;
-      if ((r = xpass(chat, s->tmp)) != NCT_OK) return r;
-      if ((r = join_projections()) != NCT_OK) return r;
       sa.tmp_in = s->tmp;
       sa.w_in = cw;
       sa.x_base = x;
       sa.alpha = R(1);
       sa.cre = R(0);
       sa.cim = R(-a / double(K - k + 1));
-      sa.Y = s->natoms ? s->Y : nullptr;
       sa.w_out = last ? out : (stage_out ? stage_out[k - 1] : s->wbuf);
       sa.tmp_out = last ? outhat : s->tmp;
       sa.W = s->natoms ? (last ? outW : s->Wwork) : nullptr;
       sa.acc = nullptr;
-      if ((r = plane_stage(sa)) != NCT_OK) return r;
+      for (int gi = 0; gi < ng; ++gi)
+        if ((r = stage_group(G[gi], cW, chat, sa)) != NCT_OK) return r;
       cw = sa.w_out;
       chat = sa.tmp_out;
       cW = sa.W;
     }
-    return NCT_OK;
+    return join_groups();
   }
 
   nct_status prepare(const void* psi, void* hat, void* W) {
@@ -1003,14 +1100,21 @@ nct_status alloc_tape(nct_system* s, nct_system::Tape& T, int cap) {
 }
 
 void free_all(nct_system* s) {
-  if (s->st2) (void)hipStreamSynchronize(s->st2);
+  for (hipStream_t q : {s->st2, s->stB, s->stB2})
+    if (q) (void)hipStreamSynchronize(q);
   for (auto& b : s->owned) (void)hipFree(b.p);
   s->owned.clear();
-  if (s->ev_rows) (void)hipEventDestroy(s->ev_rows);
-  if (s->ev_proj) (void)hipEventDestroy(s->ev_proj);
-  if (s->st2) (void)hipStreamDestroy(s->st2);
-  s->ev_rows = s->ev_proj = nullptr;
-  s->st2 = nullptr;
+  for (hipEvent_t* e : {&s->ev_rows, &s->ev_proj, &s->evB_rows, &s->evB_proj, &s->ev_fork, &s->ev_join}) {
+    if (*e) (void)hipEventDestroy(*e);
+    *e = nullptr;
+  }
+  for (hipStream_t* q : {&s->st2, &s->stB, &s->stB2}) {
+    if (*q) {
+      (void)hipStreamSynchronize(*q);
+      (void)hipStreamDestroy(*q);
+    }
+    *q = nullptr;
+  }
 }
 
 nct_status create_impl(const nct_params* p, nct_system** out) {
@@ -1119,6 +1223,25 @@ nct_status create_impl(const nct_params* p, nct_system** out) {
       hipEventCreateWithFlags(&s->ev_proj, hipEventDisableTiming) != hipSuccess) {
     fail(s, NCT_ERR_HIP, "stream/event creation failed");
     return bail(NCT_ERR_HIP);
+  }
+  if (p->overlap && s->S >= 8) {
+    s->ngroups = 2;
+    s->S0 = (s->S + 1) / 2;
+    if (hipStreamCreateWithFlags(&s->stB, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->stB2, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s->evB_rows, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->evB_proj, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming) != hipSuccess) {
+      fail(s, NCT_ERR_HIP, "stream/event creation failed");
+      return bail(NCT_ERR_HIP);
+    }
+    if (s->natoms) {
+      const size_t cp = size_t(s->natoms) * s->pt.PP * s->S;
+      if ((r = dalloc(s, cp * s->pt.max_kchunks * 16, &s->CpartB)) != NCT_OK) return bail(r);
+      if ((r = dalloc(s, cp * 16, &s->CB)) != NCT_OK) return bail(r);
+      if ((r = dalloc(s, cp * s->cbytes, &s->ECB)) != NCT_OK) return bail(r);
+    }
   }
   hipError_t e = hipMemsetAsync(s->vext, 0, N * 8, s->st);
   if (e == hipSuccess) e = hipMemsetAsync(s->fields, 0, 4 * N * 8, s->st);
@@ -1308,6 +1431,8 @@ nct_status nct_set_timing(nct_system* s, int enable) {
   if (!s) return NCT_ERR_ARG;
   HIPCHK(s, hipStreamSynchronize(s->st));
   HIPCHK(s, hipStreamSynchronize(s->st2));
+  if (s->stB) HIPCHK(s, hipStreamSynchronize(s->stB));
+  if (s->stB2) HIPCHK(s, hipStreamSynchronize(s->stB2));
   harvest_timing(s);
   for (int k = 0; k < NCT_K_COUNT; ++k) {
     s->t_ms[k] = 0;
@@ -1326,6 +1451,8 @@ nct_status nct_get_timing(nct_system* s, int k, double* ms, long long* launches,
   if (k < 0 || k >= NCT_K_COUNT) return fail(s, NCT_ERR_ARG, "kernel class out of range");
   HIPCHK(s, hipStreamSynchronize(s->st));
   HIPCHK(s, hipStreamSynchronize(s->st2));
+  if (s->stB) HIPCHK(s, hipStreamSynchronize(s->stB));
+  if (s->stB2) HIPCHK(s, hipStreamSynchronize(s->stB2));
   harvest_timing(s);
   if (ms) *ms = s->t_ms[k];
   if (launches) *launches = s->t_count[k];

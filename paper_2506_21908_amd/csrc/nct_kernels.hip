@@ -448,53 +448,70 @@ constexpr int xpass_tc(int nx) {
 }
 constexpr int XP_NT = 256;
 
-template <typename R, int NX, int TC>
+// Column pass over XP_T consecutive tiles per workgroup: the loads of tile t+1 are issued
+// before tile t is transformed, so each workgroup keeps global loads in flight during its LDS
+// work.  Tile = TC consecutive yz columns x NX planes of one batch entry (spinor component).
+// XT tiles per workgroup (XT divides the tile count; compile time, so the loop unrolls).
+template <typename R, int NX, int TC, int XT>
 __global__ __launch_bounds__(XP_NT) void k_xpass(const cpx<R>* src, cpx<R>* dst, int NYZ,
                                                  const R* __restrict__ g2x,
                                                  const R* __restrict__ g2yz, R kscale, int mode,
                                                  const cpx<R>* __restrict__ twx_g) {
   __shared__ cpx<R> tile[NX * TC];
   __shared__ cpx<R> tw[NX];
-  const int tid = threadIdx.x;
-  const int tiles = NYZ / TC;
-  const int b = blockIdx.x / tiles;
-  const int tl = blockIdx.x - b * tiles;
-  const int q0 = tl * TC;
-  for (int k = tid; k < NX; k += XP_NT) tw[k] = twx_g[k];
-  const size_t base = size_t(b) * NX * NYZ + q0;
   constexpr int PER = (NX * TC + XP_NT - 1) / XP_NT;
-  {
-    cpx<R> v[PER];
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-      const int e = min(tid + j * XP_NT, NX * TC - 1);  // clamped: every load unconditional
-      v[j] = src[base + size_t(e / TC) * NYZ + (e % TC)];
-    }
-#pragma unroll
+  const int tid = threadIdx.x;
+  const int groups = NYZ / (TC * XT);
+  const int b = blockIdx.x / groups;
+  const int t0 = (blockIdx.x - b * groups) * XT;
+  for (int k = tid; k < NX; k += XP_NT) tw[k] = twx_g[k];
+  const size_t bbase = size_t(b) * NX * NYZ;
+  R vx[PER], vy[PER];  // prefetch registers (separate real/imag arrays stay in VGPRs)
+_Pragma("clang loop unroll(full)")
+  for (int j = 0; j < PER; ++j) {
+    const int e = min(tid + j * XP_NT, NX * TC - 1);
+    const cpx<R> q = src[bbase + size_t(t0) * TC + size_t(e / TC) * NYZ + (e % TC)];
+    vx[j] = q.x;
+    vy[j] = q.y;
+  }
+_Pragma("clang loop unroll(full)")
+  for (int u = 0; u < XT; ++u) {
+    const int q0 = (t0 + u) * TC;
+_Pragma("clang loop unroll(full)")
     for (int j = 0; j < PER; ++j) {
       const int e = tid + j * XP_NT;
-      if (e < NX * TC) tile[e] = v[j];
+      if (e < NX * TC) tile[e] = cpx<R>{vx[j], vy[j]};
     }
-  }
-  __syncthreads();
-  lds_fft<R, NX, TC, 1, TC, true>(tile, tw, tid, XP_NT);
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int e = tid + j * XP_NT;
-    if (e < NX * TC) {
-      const R g = g2x[e / TC] + g2yz[q0 + (e % TC)];
-      R m;
-      if (mode == 0) m = kscale * g;
-      else m = g > R(0) ? kscale / g : R(0);
-      tile[e] = cscale(tile[e], m);
+    __syncthreads();
+    if (u + 1 < XT) {  // prefetch the next tile while this one is transformed
+_Pragma("clang loop unroll(full)")
+      for (int j = 0; j < PER; ++j) {
+        const int e = min(tid + j * XP_NT, NX * TC - 1);
+        const cpx<R> q = src[bbase + size_t(q0 + TC) + size_t(e / TC) * NYZ + (e % TC)];
+        vx[j] = q.x;
+        vy[j] = q.y;
+      }
     }
-  }
-  __syncthreads();
-  lds_fft<R, NX, TC, 1, TC, false>(tile, tw, tid, XP_NT);
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int e = tid + j * XP_NT;
-    if (e < NX * TC) dst[base + size_t(e / TC) * NYZ + (e % TC)] = tile[e];
+    lds_fft<R, NX, TC, 1, TC, true>(tile, tw, tid, XP_NT);
+_Pragma("clang loop unroll(full)")
+    for (int j = 0; j < PER; ++j) {
+      const int e = tid + j * XP_NT;
+      if (e < NX * TC) {
+        const R g = g2x[e / TC] + g2yz[q0 + (e % TC)];
+        R m;
+        if (mode == 0) m = kscale * g;
+        else m = g > R(0) ? kscale / g : R(0);
+        tile[e] = cscale(tile[e], m);
+      }
+    }
+    __syncthreads();
+    lds_fft<R, NX, TC, 1, TC, false>(tile, tw, tid, XP_NT);
+_Pragma("clang loop unroll(full)")
+    for (int j = 0; j < PER; ++j) {
+      const int e = tid + j * XP_NT;
+      if (e < NX * TC) dst[bbase + size_t(q0) + size_t(e / TC) * NYZ + (e % TC)] = tile[e];
+    }
+    __syncthreads();
   }
 }
 
@@ -1168,6 +1185,20 @@ hipError_t launch_plane_inv(const int n[3], int B, const void* in, void* out, R 
   return hipErrorInvalidValue;
 }
 
+template <typename R, int NX, int TC>
+static hipError_t launch_xpass_tc(int B, int NYZ, const void* src, void* dst, const R* g2x, const R* g2yz,
+                                  R kscale, int mode, const void* twx, hipStream_t st) {
+  const int tiles = NYZ / TC;
+  const auto s_ = reinterpret_cast<const cpx<R>*>(src);
+  const auto d_ = reinterpret_cast<cpx<R>*>(dst);
+  const auto t_ = reinterpret_cast<const cpx<R>*>(twx);
+  // one tile per workgroup: prefetching a second tile (XT > 1) measured no faster on MI355X and
+  // costs occupancy
+  hipLaunchKernelGGL((k_xpass<R, NX, TC, 1>), dim3(unsigned(B) * unsigned(tiles)), dim3(XP_NT), 0, st,
+                     s_, d_, NYZ, g2x, g2yz, kscale, mode, t_);
+  return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_xpass(const int n[3], int B, const void* src, void* dst, const R* g2x,
                         const R* g2yz, R kscale, int mode, const void* twx, hipStream_t st) {
@@ -1175,18 +1206,9 @@ hipError_t launch_xpass(const int n[3], int B, const void* src, void* dst, const
 #define X(A)                                                                                \
   if (n[0] == A) {                                                                          \
     constexpr int TCP = xpass_tc<R>(A);                                                     \
-    if (NYZ % TCP == 0) {                                                                   \
-      hipLaunchKernelGGL((k_xpass<R, A, TCP>), dim3(unsigned(B) * unsigned(NYZ / TCP)),      \
-                         dim3(XP_NT), 0, st, reinterpret_cast<const cpx<R>*>(src),           \
-                         reinterpret_cast<cpx<R>*>(dst), NYZ, g2x, g2yz, kscale, mode,       \
-                         reinterpret_cast<const cpx<R>*>(twx));                              \
-    } else {                                                                                \
-      hipLaunchKernelGGL((k_xpass<R, A, 16>), dim3(unsigned(B) * unsigned(NYZ / 16)),        \
-                         dim3(XP_NT), 0, st, reinterpret_cast<const cpx<R>*>(src),           \
-                         reinterpret_cast<cpx<R>*>(dst), NYZ, g2x, g2yz, kscale, mode,       \
-                         reinterpret_cast<const cpx<R>*>(twx));                              \
-    }                                                                                       \
-    return hipGetLastError();                                                               \
+    if (NYZ % TCP == 0)                                                                     \
+      return launch_xpass_tc<R, A, TCP>(B, NYZ, src, dst, g2x, g2yz, kscale, mode, twx, st); \
+    return launch_xpass_tc<R, A, 16>(B, NYZ, src, dst, g2x, g2yz, kscale, mode, twx, st);   \
   }
   NCT_LINES(X)
 #undef X

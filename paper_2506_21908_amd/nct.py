@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
                 ("nchannels", c_int), ("channels", POINTER(Channel)), ("r_sphere", c_double),
                 ("xc", c_int), ("hartree", c_int), ("m_threshold", c_double), ("dt", c_double),
                 ("taylor_order", c_int), ("precision", c_int), ("tape_steps", c_int),
-                ("stream", c_void_p)]
+                ("overlap", c_int), ("stream", c_void_p)]
 
 
 class NctError(RuntimeError):
@@ -118,7 +118,7 @@ class System:
                  positions=None, channels=(), r_sphere: float = 2.5, xc: int = 1,
                  hartree: int = 1, m_threshold: float = 1e-12, dt: float = 0.05,
                  taylor_order: int = 4, precision: int = NCT_FP64, tape_steps: int = 0,
-                 stream=None):
+                 overlap: bool = False, stream=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("nct.System needs a GPU (no CPU fallback)")
@@ -150,6 +150,7 @@ class System:
         p.taylor_order = int(taylor_order)
         p.precision = int(precision)
         p.tape_steps = int(tape_steps)
+        p.overlap = int(bool(overlap))
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -251,14 +252,14 @@ class System:
 
 
 def system_from_workload(w, precision: int = NCT_FP64, tape_steps: int = 0, dt=None,
-                         taylor_order=None, stream=None) -> System:
+                         taylor_order=None, overlap: bool = False, stream=None) -> System:
     """Create a System for a seeded workload and upload its v_ext and B field."""
     import torch
     s = System(w.n, w.L, w.nstates, occ=w.occ, positions=w.positions, channels=w.channels,
                r_sphere=w.r_sphere, xc=w.xc, hartree=w.hartree, m_threshold=w.m_threshold,
                dt=w.dt if dt is None else dt,
                taylor_order=w.taylor_order if taylor_order is None else taylor_order,
-               precision=precision, tape_steps=tape_steps, stream=stream)
+               precision=precision, tape_steps=tape_steps, overlap=overlap, stream=stream)
     v = torch.from_numpy(np.ascontiguousarray(w.v_ext)).to("cuda")
     s.set_potentials(v_ext=v, B0=w.bfield.B0, pulses=w.bfield.pulses)
     torch.cuda.synchronize()

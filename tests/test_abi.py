@@ -42,9 +42,9 @@ def test_ctypes_structs_match_c_layout():
 #include "nct.h"
 int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(nct_channel), sizeof(nct_pulse), sizeof(nct_bfield), sizeof(nct_params));
-  printf("%zu %zu %zu %zu %zu %zu\n", offsetof(nct_params, nstates), offsetof(nct_params, occ),
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", offsetof(nct_params, nstates), offsetof(nct_params, occ),
          offsetof(nct_params, r_sphere), offsetof(nct_params, dt), offsetof(nct_params, tape_steps),
-         offsetof(nct_params, stream));
+         offsetof(nct_params, overlap), offsetof(nct_params, stream));
   printf("%zu %zu\n", offsetof(nct_pulse, e1), offsetof(nct_bfield, pulses));
   return 0;
 }
@@ -59,9 +59,9 @@ int main(void) {
     P = nct.Params
     assert vals[:4] == [ctypes.sizeof(nct.Channel), ctypes.sizeof(nct.Pulse),
                         ctypes.sizeof(nct.BField), ctypes.sizeof(P)]
-    assert vals[4:10] == [P.nstates.offset, P.occ.offset, P.r_sphere.offset, P.dt.offset,
-                          P.tape_steps.offset, P.stream.offset]
-    assert vals[10:12] == [nct.Pulse.e1.offset, nct.BField.pulses.offset]
+    assert vals[4:11] == [P.nstates.offset, P.occ.offset, P.r_sphere.offset, P.dt.offset,
+                          P.tape_steps.offset, P.overlap.offset, P.stream.offset]
+    assert vals[11:13] == [nct.Pulse.e1.offset, nct.BField.pulses.offset]
 
 
 def test_binding_refuses_without_gpu():

@@ -224,6 +224,23 @@ def test_step_cluster_workload_fp64_one_step(torch_cuda):
     assert en < 1e-10 and em < 1e-10
 
 
+def test_step_overlap_groups_bitwise(torch_cuda):
+    """The two-stream state-group schedule gives bit-identical trajectories (same kernels per state)."""
+    nct = nct_mod()
+    bf = I.BField(pulses=I.circular_pulses([0.1], [0.5], 0.05, 0.1))
+    w = I.make_system(n=(16, 16, 16), L=(8.0,) * 3, nstates=9, natoms=2, case=27, bfield=bf,
+                      full_spinors=False, min_sep=4.0)
+    say("overlap groups S=9")
+    out = []
+    for ov in (False, True):
+        s = nct.system_from_workload(w, overlap=ov)
+        psi = nct.states_to_device(w.psi0)
+        obs = s.step(psi, 0.0, 3, obs=True)
+        out.append((psi.cpu().numpy(), obs))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
 def test_step_tiny_workload_mixed(torch_cuda):
     """FP32-mixed form on the tiny system: n, m, E within 1e-5 of the FP64 oracle over 20 steps."""
     nct = nct_mod()

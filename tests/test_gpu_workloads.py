@@ -1,0 +1,118 @@
+"""Full-size benchmark-shaped systems on the GPU.
+
+* Solid-like system (64^3 grid, 256 spinor states, 16 atoms x 18 KB+SOC projectors, circular
+  B pulse): one FP64 step against the CPU oracle, then 1000 steps of the FP32-mixed form
+  against 1000 steps of the FP64 path (which stands in for the oracle over the long window,
+  having matched it to 1e-10 over the windows the oracle can afford).
+* Large system (96^3 grid, 512 spinor states, 32 atoms): a few FP32-mixed steps (conservation
+  of N_e and norms) and one adjoint step in recompute mode (memory schedule on 288 GB).
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import nct_oracle as O
+from paper_2506_21908_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def solid():
+    return I.workload(2)
+
+
+def _traj_errors(obs, ref):
+    """Relative errors of N_e, M and E over a trajectory (rows of the 13-column observables)."""
+    e_N = np.max(np.abs(obs[:, 1] - ref[:, 1])) / abs(ref[0, 1])
+    e_M = np.max(np.abs(obs[:, 2:5] - ref[:, 2:5])) / max(np.max(np.abs(ref[:, 2:5])), 1.0)
+    e_E = np.max(np.abs(obs[:, 5] - ref[:, 5])) / abs(ref[0, 5])
+    return e_N, e_M, e_E
+
+
+def _nm_errors(psi_a, psi_b, occ):
+    ra, rb = O.spin_density(psi_a, occ), O.spin_density(psi_b, occ)
+    na, ma = O.charge_and_magnetization(ra)
+    nb, mb = O.charge_and_magnetization(rb)
+    return (np.linalg.norm(na - nb) / np.linalg.norm(nb), np.linalg.norm(ma - mb) / np.linalg.norm(nb))
+
+
+def test_solid_workload_fp64_one_step_vs_oracle(torch_cuda, solid):
+    from paper_2506_21908_amd import nct
+    w = solid
+    say(f"{w.name}: 1 FP64 step vs oracle")
+    sysd = O.system_from_workload(w)
+    t0 = time.time()
+    psi_ref, obs_ref = O.run(sysd, w.psi0, 1)
+    say(f"  oracle step {time.time() - t0:.1f} s")
+    s = nct.system_from_workload(w)
+    psi = nct.states_to_device(w.psi0)
+    obs = s.step(psi, 0.0, 1, obs=True)
+    e_N, e_M, e_E = _traj_errors(obs, obs_ref[1:])
+    en, em = _nm_errors(psi.cpu().numpy(), psi_ref, sysd.occ)
+    say(f"  N_e {e_N:.2e} M {e_M:.2e} E {e_E:.2e} n {en:.2e} m {em:.2e}")
+    assert max(e_N, e_M, e_E, en, em) < 1e-10
+
+
+def test_solid_workload_mixed_vs_fp64_1000_steps(torch_cuda, solid):
+    """FP32-mixed form (complex64 states, FP32 FFT / local multiply / MFMA projectors; FP64
+    densities, exchange, Poisson and reductions) within 1e-5 of FP64 over 1000 steps."""
+    from paper_2506_21908_amd import nct
+    w = solid
+    nsteps = 1000
+    res = {}
+    for prec in (nct.NCT_FP64, nct.NCT_FP32_MIXED):
+        say(f"{w.name}: {nsteps} steps precision={prec}")
+        s = nct.system_from_workload(w, precision=prec)
+        psi = nct.states_to_device(w.psi0, prec)
+        t0 = time.time()
+        obs = s.step(psi, 0.0, nsteps, obs=True)
+        say(f"  {time.time() - t0:.1f} s")
+        res[prec] = (obs, psi.cpu().numpy().astype(np.complex128))
+        s.close()
+        del psi
+        torch_cuda.cuda.empty_cache()
+    (o64, p64), (o32, p32) = res[nct.NCT_FP64], res[nct.NCT_FP32_MIXED]
+    e_N, e_M, e_E = _traj_errors(o32, o64)
+    en, em = _nm_errors(p32, p64, w.occ)
+    say(f"  mixed vs fp64 over {nsteps} steps: N_e {e_N:.2e} M {e_M:.2e} E {e_E:.2e} "
+        f"final n {en:.2e} m {em:.2e}; M_z(T) fp64 {o64[-1, 4]:.10f} mixed {o32[-1, 4]:.10f}")
+    assert max(e_N, e_M, e_E, en, em) < 1e-5
+
+
+def test_large_workload_mixed_steps_and_adjoint(torch_cuda):
+    """96^3 x 512 spinors, 32 atoms: FP32-mixed steps conserve N_e and norms; one recompute-mode
+    adjoint step runs within memory and its seed/gradient are finite."""
+    torch = torch_cuda
+    from paper_2506_21908_amd import nct
+    w = I.workload(4)
+    say(f"{w.name}: 3 mixed steps + 1 adjoint step")
+    s = nct.system_from_workload(w, precision=nct.NCT_FP32_MIXED, tape_steps=0)
+    psi = nct.states_to_device(w.psi0, nct.NCT_FP32_MIXED)
+    del w.psi0
+    obs = s.step(psi, 0.0, 3, obs=True)
+    say(f"  N_e {obs[:, 1]}  max norm err {obs[:, 12]}")
+    assert np.allclose(obs[:, 1], 512.0, rtol=1e-5)
+    assert np.all(obs[:, 12] < 1e-4)
+    lam = torch.empty_like(psi)
+    s.magnetization_seed(psi, (0.0, 0.0, 1.0), lam)
+    grad = np.zeros(8)
+    dLdB = s.backward_step(-1, psi, 3 * w.dt, lam, lam, grad)
+    say(f"  dL/dB {dLdB}  dL/dtheta {grad}")
+    assert np.all(np.isfinite(dLdB)) and np.all(np.isfinite(grad))
+    assert torch.isfinite(torch.view_as_real(lam)).all()
