@@ -97,6 +97,7 @@ struct nct_system {
   void* phihat = nullptr;
   void* wbuf = nullptr;
   void* tmp = nullptr;
+  void* tmpk_phi = nullptr;   // kinetic column pass of phi (shared by the 2nd and 3rd exponentials)
 
   // projectors
   ProjTables pt;
@@ -663,7 +664,10 @@ struct Engine {
   // One H application of a state group: projector chain of rows cW (second stream, joined
   // before the plane pass), column pass of chat into tmp, fused plane pass described by sa
   // (full-size pointers; offset here to the group).
-  nct_status stage_group(const Group& g, const void* cW, const void* chat, const StageArgs<R>& sa_full) {
+  // kin_dst: column-pass output buffer (default s->tmp); chat == nullptr: skip the column pass,
+  // sa_full.tmp_in already holds it.
+  nct_status stage_group(const Group& g, const void* cW, const void* chat, const StageArgs<R>& sa_full,
+                         void* kin_dst = nullptr) {
     nct_status r;
     const double frac = double(g.S) / double(s->S);
     if (s->natoms) {
@@ -682,10 +686,13 @@ struct Engine {
         return r;
       HIPCHK(s, hipEventRecord(g.ev_proj, g.st2));
     }
-    if ((r = check(timed_on(s, g.st, NCT_K_XPASS, 2 * psiB() * frac, 0, [&] {
-           return launch_xpass<R>(s->n, 2 * g.S, offs(chat, g.i0), offs(s->tmp, g.i0), g2x(), g2yz(),
-                                  R(0.5 / double(s->N)), 0, twx(), g.st); }), "xpass")) != NCT_OK)
-      return r;
+    if (chat) {
+      void* dst = kin_dst ? kin_dst : s->tmp;
+      if ((r = check(timed_on(s, g.st, NCT_K_XPASS, 2 * psiB() * frac, 0, [&] {
+             return launch_xpass<R>(s->n, 2 * g.S, offs(chat, g.i0), offs(dst, g.i0), g2x(), g2yz(),
+                                    R(0.5 / double(s->N)), 0, twx(), g.st); }), "xpass")) != NCT_OK)
+        return r;
+    }
     if (s->natoms) HIPCHK(s, hipStreamWaitEvent(g.st, g.ev_proj, 0));
     StageArgs<R> sa = sa_full;
     sa.tmp_in = offs(sa.tmp_in, g.i0);
@@ -712,8 +719,11 @@ struct Engine {
 
   // T_K(-i a H) x by Horner stages w_k = x + (-i a/(K-k+1)) H w_{k-1}, w_0 = x.
   // stage_out[k-1] (k = 1..K-1), if given, receives w_k (the adjoint tape); else the work buffer.
+  // kin_save: keep the first stage's column pass in this buffer; kin_reuse: take the first
+  // stage's column pass from this buffer instead of recomputing it (same x, fields-independent).
   nct_status taylor(const void* x, const void* xhat, const void* xW, void* out, void* outhat,
-                    void* outW, double t, void* const* stage_out = nullptr) {
+                    void* outW, double t, void* const* stage_out = nullptr, void* kin_save = nullptr,
+                    const void* kin_reuse = nullptr) {
     const int K = s->prm.taylor_order;
     const double a = 0.5 * s->prm.dt;
     const void* cw = x;
@@ -728,7 +738,10 @@ struct Engine {
     if ((r = fork_groups()) != NCT_OK) return r;
     for (int k = 1; k <= K; ++k) {
       const bool last = (k == K);
+      const bool first = (k == 1);
       sa.tmp_in = s->tmp;
+      if (first && kin_reuse) sa.tmp_in = kin_reuse;
+      if (first && kin_save) sa.tmp_in = kin_save;
       sa.w_in = cw;
       sa.x_base = x;
       sa.alpha = R(1);
@@ -739,7 +752,9 @@ struct Engine {
       sa.W = s->natoms ? (last ? outW : s->Wwork) : nullptr;
       sa.acc = nullptr;
       for (int gi = 0; gi < ng; ++gi)
-        if ((r = stage_group(G[gi], cW, chat, sa)) != NCT_OK) return r;
+        if ((r = stage_group(G[gi], cW, (first && kin_reuse) ? nullptr : chat, sa,
+                             first ? kin_save : nullptr)) != NCT_OK)
+          return r;
       cw = sa.w_out;
       chat = sa.tmp_out;
       cW = sa.W;
@@ -844,14 +859,16 @@ struct Engine {
       }
       if ((r = taylor(cur, s->psihat, s->Wpsi, phi, s->phihat, s->Wphi, t, T ? so1.data() : nullptr)) != NCT_OK)
         return r;
-      if ((r = taylor(phi, s->phihat, s->Wphi, ptil, nullptr, nullptr, t, T ? so2.data() : nullptr)) != NCT_OK)
+      if ((r = taylor(phi, s->phihat, s->Wphi, ptil, nullptr, nullptr, t, T ? so2.data() : nullptr,
+                      s->tmpk_phi)) != NCT_OK)
         return r;
       if (!s->frozen) {
         if ((r = density(ptil)) != NCT_OK) return r;
         if ((r = fields_from_rho(true)) != NCT_OK) return r;
       }
       if (T && (r = save_fields(*T, k, 1)) != NCT_OK) return r;
-      if ((r = taylor(phi, s->phihat, s->Wphi, next, s->psihat, s->Wpsi, t + dt, T ? so3.data() : nullptr)) != NCT_OK)
+      if ((r = taylor(phi, s->phihat, s->Wphi, next, s->psihat, s->Wpsi, t + dt, T ? so3.data() : nullptr,
+                      nullptr, s->tmpk_phi)) != NCT_OK)
         return r;
       cur = next;
       if (!s->frozen || obs_host) {
@@ -1202,6 +1219,7 @@ nct_status create_impl(const nct_params* p, nct_system** out) {
   if ((r = dalloc(s, psib, &s->phihat)) != NCT_OK) return bail(r);
   if ((r = dalloc(s, psib, &s->wbuf)) != NCT_OK) return bail(r);
   if ((r = dalloc(s, psib, &s->tmp)) != NCT_OK) return bail(r);
+  if ((r = dalloc(s, psib, &s->tmpk_phi)) != NCT_OK) return bail(r);
   if (s->fp64) r = build_projectors<double>(s);
   else r = build_projectors<float>(s);
   if (r != NCT_OK) return bail(r);

@@ -201,7 +201,18 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a
 // Same stage as k_plane_stage, with the two spinor components of the (state, x-plane) held as
 // two LDS planes and transformed concurrently by the two halves of the workgroup; the pointwise
 // 2x2 update then reads both planes.  Used when two planes fit in LDS.
-__host__ __device__ constexpr int plane2_nth(int np) { return plane_nt(np) > 512 ? 512 : plane_nt(np); }
+// Threads per spinor half: plane_nt's choice capped at NCT_PLANE2_NTH_MAX (tuning macro).
+#ifndef NCT_PLANE2_NTH_MAX_F64
+#define NCT_PLANE2_NTH_MAX_F64 512
+#endif
+#ifndef NCT_PLANE2_NTH_MAX_F32
+#define NCT_PLANE2_NTH_MAX_F32 512
+#endif
+template <typename R>
+__host__ __device__ constexpr int plane2_nth(int np) {
+  const int cap = sizeof(R) == 8 ? NCT_PLANE2_NTH_MAX_F64 : NCT_PLANE2_NTH_MAX_F32;
+  return plane_nt(np) > cap ? cap : plane_nt(np);
+}
 template <int NY, int NZ>
 constexpr size_t plane2_lds_bytes(size_t elem) {
   return (size_t(2) * NY * (NZ + 1) + NY + NZ) * elem;
@@ -212,18 +223,24 @@ constexpr bool plane2_fits() {
 }
 
 template <typename R, int NY, int NZ>
-__global__ __launch_bounds__(2 * plane2_nth(NY* NZ)) void k_plane_stage2(StageArgs<R> a, ProjTables pt,
+__global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(StageArgs<R> a, ProjTables pt,
                                                                           const cpx<R>* __restrict__ twy_g,
                                                                           const cpx<R>* __restrict__ twz_g,
                                                                           int S, int NX) {
   constexpr int NP = NY * NZ;
-  constexpr int NTH = plane2_nth(NP);
+  constexpr int NTH = plane2_nth<R>(NP);
   constexpr int NT = 2 * NTH;
   constexpr int PZ = NZ + 1;
   constexpr int PL = NY * PZ;
   constexpr int PPH = (NP + NTH - 1) / NTH;
   constexpr int PPT = (NP + NT - 1) / NT;
-  constexpr int G = sizeof(R) == 8 ? 3 : 5;  // pointwise points per load batch
+#ifndef NCT_PLANE2_G_F64
+#define NCT_PLANE2_G_F64 3
+#endif
+#ifndef NCT_PLANE2_G_F32
+#define NCT_PLANE2_G_F32 3
+#endif
+  constexpr int G = sizeof(R) == 8 ? NCT_PLANE2_G_F64 : NCT_PLANE2_G_F32;  // pointwise points per load batch
   extern __shared__ double4 smem_d4[];
   cpx<R>* planes = reinterpret_cast<cpx<R>*>(smem_d4);
   cpx<R>* twy = planes + 2 * PL;
@@ -1121,7 +1138,7 @@ hipError_t launch_plane_stage(const int n[3], int S, const StageArgs<R>& a, cons
       auto kern2 = k_plane_stage2<R, A, B>;                                                 \
       hipError_t e2 = set_lds(kern2, lds2);                                                 \
       if (e2 != hipSuccess) return e2;                                                      \
-      hipLaunchKernelGGL(kern2, dim3(grid), dim3(2 * plane2_nth(A * B)), lds2, st, a, pt,   \
+      hipLaunchKernelGGL(kern2, dim3(grid), dim3(2 * plane2_nth<R>(A * B)), lds2, st, a, pt,   \
                          reinterpret_cast<const cpx<R>*>(twy), reinterpret_cast<const cpx<R>*>(twz), \
                          S, n[0]);                                                          \
       return hipGetLastError();                                                             \
