@@ -879,6 +879,10 @@ struct Engine {
         if ((r = obs_row(t + dt, s->obs_dev + size_t(k) * kObsWidth)) != NCT_OK) return r;
       }
     }
+    if (s->frozen && !obs_host) {  // frozen fields: one density at the end for the finiteness check
+      if ((r = density(cur)) != NCT_OK) return r;
+      if ((r = fields_from_rho(false)) != NCT_OK) return r;
+    }
     double tot[8];
     HIPCHK(s, hipMemcpyAsync(tot, s->ftot, sizeof(tot), hipMemcpyDeviceToHost, s->st));
     if (obs_host)
@@ -887,8 +891,7 @@ struct Engine {
     HIPCHK(s, hipStreamSynchronize(s->st));
     harvest_timing(s);
     if (T) T->valid = nsteps;
-    if ((!s->frozen || obs_host) && !std::isfinite(tot[0]))
-      return fail(s, NCT_ERR_NONFINITE, "non-finite electron count after step");
+    if (!std::isfinite(tot[0])) return fail(s, NCT_ERR_NONFINITE, "non-finite electron count after step");
     return NCT_OK;
   }
 

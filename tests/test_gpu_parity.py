@@ -46,7 +46,7 @@ def random_fields(n, seed):
 # ------------------------------------------------------------------ single H application
 @pytest.mark.parametrize("n,S", [((8, 8, 8), 3), ((12, 16, 12), 5), ((16, 8, 16), 2),
                                  ((24, 16, 24), 3), ((16, 16, 16), 4), ((32, 32, 32), 2),
-                                 ((48, 48, 48), 2), ((64, 64, 64), 1)])
+                                 ((48, 48, 48), 2), ((64, 64, 64), 1), ((96, 96, 96), 1)])
 def test_apply_hamiltonian_frozen_fields(torch_cuda, n, S):
     """H psi = T psi + [v + b.sigma] psi with frozen random fields, no projectors."""
     torch = torch_cuda
@@ -276,6 +276,103 @@ def test_frozen_field_step(torch_cuda):
     psi = nct.states_to_device(w.psi0)
     s.step(psi, 0.0, 3)
     assert rel(psi.cpu().numpy(), ref) < 1e-12
+
+
+def test_apply_hamiltonian_96_mixed(torch_cuda):
+    """96^2 planes in FP32 (two-half plane pass at its largest LDS footprint).  The oracle sees
+    the same FP32-rounded states and fields, so only the kernel's FP32 arithmetic is measured; the
+    error of an FP32 FFT round trip grows like u log2(N) (u = 2^-24, the FP32 unit roundoff), and
+    the bound 8 u log2(N) (about 9.4e-6 for N = 96^3) stays inside the FP32-mixed tolerance of
+    1e-5."""
+    torch = torch_cuda
+    nct = nct_mod()
+    n = (96, 96, 96)
+    say("apply_H mixed 96^3")
+    w = I.make_system(n=n, L=(40.0,) * 3, nstates=1, case=28, natoms=0)
+    F = random_fields(n, 5).astype(np.float32).astype(np.float64)
+    psi32 = w.psi0.astype(np.complex64)
+    psi_in = psi32.astype(np.complex128)
+    sysd = O.system_from_workload(w)
+    ref = O.kinetic(psi_in, sysd.grid) + O.apply_local(psi_in, F[0], F[1:])
+    s = nct.system_from_workload(w, precision=nct.NCT_FP32_MIXED)
+    s.set_potentials(fields=torch.from_numpy(F).cuda())
+    psi = nct.states_to_device(psi32, nct.NCT_FP32_MIXED)
+    hpsi = torch.empty_like(psi)
+    s.apply_hamiltonian(psi, hpsi, 0.0)
+    tol = 8 * 2.0 ** -24 * np.log2(np.prod(n))
+    err = rel(hpsi.cpu().numpy().astype(np.complex128), ref)
+    say(f"  rel err {err:.2e} (tol {tol:.2e})")
+    assert err < tol
+
+
+@pytest.mark.parametrize("xc", [0, 1])
+def test_step_single_state_and_noncubic_projectors(torch_cuda, xc):
+    """S = 1 (15 padded states in every MFMA tile) on a 12x16x12 grid with projectors and a
+    static field, against the oracle.  One spinor is fully polarised at every point, so the
+    minority density n_- = (n - |m|)/2 is zero up to rounding and Slater's n_-^(1/3) magnifies
+    rounding noise: with exchange on, the oracle itself moves by ~1e-10 in psi when its input
+    is perturbed at 1e-16.  The bound on psi is then a small multiple of that measured
+    sensitivity; without exchange the dynamics is well conditioned and psi must agree to 1e-12.
+    Observables are insensitive in both cases."""
+    nct = nct_mod()
+    say(f"S=1 non-cubic projectors xc={xc}")
+    w = I.make_system(n=(12, 16, 12), L=(6.5, 8.0, 6.5), nstates=1, natoms=1, case=29,
+                      bfield=I.BField(B0=(0.03, 0.0, -0.02)), full_spinors=True, xc=xc)
+    sysd = O.system_from_workload(w)
+    psi_ref, obs_ref = O.run(sysd, w.psi0, 4)
+    rng = np.random.default_rng(1)
+    psi_p, _ = O.run(sysd, w.psi0 * (1 + 1e-16 * rng.standard_normal(w.psi0.shape)), 4)
+    sens = rel(psi_p, psi_ref)
+    s = nct.system_from_workload(w)
+    psi = nct.states_to_device(w.psi0)
+    obs = s.step(psi, 0.0, 4, obs=True)
+    _compare_traj(obs, obs_ref[1:], 1e-10)
+    err = rel(psi.cpu().numpy(), psi_ref)
+    say(f"  psi err {err:.2e}, oracle sensitivity {sens:.2e}")
+    assert err < max(10 * sens, 1e-12)
+    if xc == 0:
+        assert sens < 1e-14
+
+
+def test_tape_and_backward_argument_errors(torch_cuda):
+    torch = torch_cuda
+    nct = nct_mod()
+    say("tape errors")
+    w = I.make_system(n=(8, 8, 8), L=(6.0,) * 3, nstates=2, case=31)
+    s = nct.system_from_workload(w, tape_steps=2)
+    psi = nct.states_to_device(w.psi0)
+    lam = torch.zeros_like(psi)
+    with pytest.raises(nct.NctError) as e:       # nothing taped yet
+        s.backward_step(0, None, 0.0, lam, lam)
+    assert e.value.code == nct.NCT_ERR_STATE
+    with pytest.raises(nct.NctError) as e:       # more steps than the tape holds
+        s.step(psi, 0.0, 3, tape=True)
+    assert e.value.code == nct.NCT_ERR_ARG
+    s.step(psi, 0.0, 2, tape=True)
+    with pytest.raises(nct.NctError) as e:       # index beyond the record
+        s.backward_step(2, None, 0.1, lam, lam)
+    assert e.value.code == nct.NCT_ERR_STATE
+    with pytest.raises(nct.NctError) as e:       # time does not match the record
+        s.backward_step(1, None, 0.3, lam, lam)
+    assert e.value.code == nct.NCT_ERR_ARG
+    with pytest.raises(nct.NctError) as e:       # recompute mode needs psi_n
+        s.backward_step(-1, None, 0.0, lam, lam)
+    assert e.value.code == nct.NCT_ERR_ARG
+
+
+def test_frozen_nonfinite_fields_detected(torch_cuda):
+    torch = torch_cuda
+    nct = nct_mod()
+    say("frozen NaN field")
+    w = I.make_system(n=(8, 8, 8), L=(6.0,) * 3, nstates=2, case=32)
+    F = random_fields(w.n, 6)
+    F[0, 1, 1, 1] = np.nan
+    s = nct.system_from_workload(w)
+    s.set_potentials(fields=torch.from_numpy(F).cuda())
+    psi = nct.states_to_device(w.psi0)
+    with pytest.raises(nct.NctError) as e:
+        s.step(psi, 0.0, 1)
+    assert e.value.code == nct.NCT_ERR_NONFINITE
 
 
 # ------------------------------------------------------------------ error handling
