@@ -44,6 +44,8 @@ struct StageArgs {
   void* W = nullptr;              // output sphere rows [S][2][Jtot] of w_out, or null
   // adjoint extras: acc += w_out (if acc != null)
   void* acc = nullptr;
+  // cache policy of the state-sized operands: 0 plain, 1 streaming stores, 2 streaming loads too
+  int cache_mode = 0;
 };
 
 // Launchers (return hipError_t of the launch).  n = {NX, NY, NZ}.
@@ -61,9 +63,11 @@ hipError_t launch_plane_inv(const int n[3], int B, const void* in, void* out, R 
                             const void* twy, const void* twz, hipStream_t st);
 // Column pass along x: dst = IDFT_x( mult * DFT_x(src) ), mult from per-axis |G|^2 tables.
 // mode 0: mult = kscale (g2x + g2yz); mode 1: mult = kscale / (g2x + g2yz), 0 at G = 0.
+// cache_mode as in StageArgs.
 template <typename R>
 hipError_t launch_xpass(const int n[3], int B, const void* src, void* dst, const R* g2x,
-                        const R* g2yz, R kscale, int mode, const void* twx, hipStream_t st);
+                        const R* g2yz, R kscale, int mode, const void* twx, hipStream_t st,
+                        int cache_mode = 0);
 // Energy pass: per (batch, tile) partial sums of sum kscale*G^2 |X|^2 and sum |X|^2 of the full
 // 3D transform (input in the 2D-transformed form).  part: [B][ntiles][2] doubles.
 template <typename R>

@@ -50,8 +50,37 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;  // valid on thread 0
 }
 
+// ---------------------------------------------------------------- streamed global access
+// Cache policy of the large streamed operands (the state-sized buffers), chosen per system from
+// the size of one state set: M = 0 plain loads and stores; M = 1 non-temporal (streaming)
+// stores; M = 2 non-temporal loads as well.  Streaming keeps buffers that will not be re-read
+// from the caches before eviction from displacing the shared fields and twiddles; for state
+// sets small enough to stay cache-resident between passes plain accesses are faster.
+template <int M, typename R>
+__device__ __forceinline__ cpx<R> ld_stream(const cpx<R>* p) {
+  if constexpr (M >= 2) {
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    const v2 t = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    return cpx<R>{t.x, t.y};
+  } else {
+    return *p;
+  }
+}
+template <int M, typename R>
+__device__ __forceinline__ void st_stream(cpx<R>* p, cpx<R> v) {
+  if constexpr (M >= 1) {
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    v2 t;
+    t.x = v.x;
+    t.y = v.y;
+    __builtin_nontemporal_store(t, reinterpret_cast<v2*>(p));
+  } else {
+    *p = v;
+  }
+}
+
 // ---------------------------------------------------------------- plane pass: fused H stage
-template <typename R, int NY, int NZ>
+template <typename R, int NY, int NZ, int M>
 __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a, ProjTables pt,
                                                                    const cpx<R>* __restrict__ twy_g,
                                                                    const cpx<R>* __restrict__ twz_g,
@@ -83,7 +112,7 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       const int e = tid + j * NT;
-      if (e < NP) plane[(e / NZ) * PZ + (e % NZ)] = tin[off[s] + e];
+      if (e < NP) plane[(e / NZ) * PZ + (e % NZ)] = ld_stream<M>(&tin[off[s] + e]);
     }
     __syncthreads();
     plane_fft_inv<R, NY, NZ, PZ>(plane, twy, twz, tid, NT);
@@ -108,8 +137,8 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a
       const R bx = F[N + p] + a.bext[0];
       const R by = F[2 * N + p] + a.bext[1];
       const R bz = F[3 * N + p] + a.bext[2];
-      const cpx<R> wu = win[off[0] + e];
-      const cpx<R> wd = win[off[1] + e];
+      const cpx<R> wu = ld_stream<M>(&win[off[0] + e]);
+      const cpx<R> wd = ld_stream<M>(&win[off[1] + e]);
       // up' = (v+bz) up + (bx - i by) dn ; dn' = (bx + i by) up + (v - bz) dn
       cpx<R> hu, hd;
       hu.x = hv[0][j].x + (v + bz) * wu.x + bx * wd.x + by * wd.y;
@@ -119,8 +148,8 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a
       cpx<R> ou = {a.cre * hu.x - a.cim * hu.y, a.cre * hu.y + a.cim * hu.x};
       cpx<R> od = {a.cre * hd.x - a.cim * hd.y, a.cre * hd.y + a.cim * hd.x};
       if (xb) {
-        const cpx<R> xu = xb[off[0] + e];
-        const cpx<R> xd = xb[off[1] + e];
+        const cpx<R> xu = ld_stream<M>(&xb[off[0] + e]);
+        const cpx<R> xd = ld_stream<M>(&xb[off[1] + e]);
         ou.x += a.alpha * xu.x;
         ou.y += a.alpha * xu.y;
         od.x += a.alpha * xd.x;
@@ -176,7 +205,7 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a
         const int e = tid + j * NT;
         if (e < NP) {
           const cpx<R> o = plane[(e / NZ) * PZ + (e % NZ)];
-          if (wout) wout[off[s] + e] = o;
+          if (wout) st_stream<M>(&wout[off[s] + e], o);
           if (acc) {
             cpx<R> q = acc[off[s] + e];
             acc[off[s] + e] = q + o;
@@ -190,7 +219,7 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
         const int e = tid + j * NT;
-        if (e < NP) tout[off[s] + e] = plane[(e / NZ) * PZ + (e % NZ)];
+        if (e < NP) st_stream<M>(&tout[off[s] + e], plane[(e / NZ) * PZ + (e % NZ)]);
       }
     }
     __syncthreads();
@@ -222,7 +251,7 @@ constexpr bool plane2_fits() {
   return plane2_lds_bytes<NY, NZ>(sizeof(cpx<R>)) <= 160 * 1024 - 1024;
 }
 
-template <typename R, int NY, int NZ>
+template <typename R, int NY, int NZ, int M>
 __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(StageArgs<R> a, ProjTables pt,
                                                                           const cpx<R>* __restrict__ twy_g,
                                                                           const cpx<R>* __restrict__ twz_g,
@@ -264,7 +293,7 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(Stag
     const cpx<R>* __restrict__ tin = reinterpret_cast<const cpx<R>*>(a.tmp_in);
     cpx<R> v[PPH];
 #pragma unroll
-    for (int j = 0; j < PPH; ++j) v[j] = tin[offh + min(th + j * NTH, NP - 1)];
+    for (int j = 0; j < PPH; ++j) v[j] = ld_stream<M>(&tin[offh + min(th + j * NTH, NP - 1)]);
 #pragma unroll
     for (int j = 0; j < PPH; ++j) {
       const int e = th + j * NTH;
@@ -289,11 +318,11 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(Stag
         if (j0 + g < PPT) {
           const int e = min(tid + (j0 + g) * NT, NP - 1);  // clamped: loads unconditional
           const size_t p = size_t(x) * NP + e;
-          wu[g] = win[off0 + e];
-          wd[g] = win[off1 + e];
+          wu[g] = ld_stream<M>(&win[off0 + e]);
+          wd[g] = ld_stream<M>(&win[off1 + e]);
           if (xsep) {
-            xu[g] = xb[off0 + e];
-            xd[g] = xb[off1 + e];
+            xu[g] = ld_stream<M>(&xb[off0 + e]);
+            xd[g] = ld_stream<M>(&xb[off1 + e]);
           } else {
             xu[g] = wu[g];
             xd[g] = wd[g];
@@ -377,7 +406,7 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(Stag
 #pragma unroll
     for (int j = 0; j < PPH; ++j) {
       const int e = th + j * NTH;
-      if (e < NP) wout[offh + e] = pl[(e / NZ) * PZ + (e % NZ)];
+      if (e < NP) st_stream<M>(&wout[offh + e], pl[(e / NZ) * PZ + (e % NZ)]);
     }
   }
   if (tout) {
@@ -386,7 +415,7 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(Stag
 #pragma unroll
     for (int j = 0; j < PPH; ++j) {
       const int e = th + j * NTH;
-      if (e < NP) tout[offh + e] = pl[(e / NZ) * PZ + (e % NZ)];
+      if (e < NP) st_stream<M>(&tout[offh + e], pl[(e / NZ) * PZ + (e % NZ)]);
     }
   }
 }
@@ -469,7 +498,7 @@ constexpr int XP_NT = 256;
 // before tile t is transformed, so each workgroup keeps global loads in flight during its LDS
 // work.  Tile = TC consecutive yz columns x NX planes of one batch entry (spinor component).
 // XT tiles per workgroup (XT divides the tile count; compile time, so the loop unrolls).
-template <typename R, int NX, int TC, int XT>
+template <typename R, int NX, int TC, int XT, int M>
 __global__ __launch_bounds__(XP_NT) void k_xpass(const cpx<R>* src, cpx<R>* dst, int NYZ,
                                                  const R* __restrict__ g2x,
                                                  const R* __restrict__ g2yz, R kscale, int mode,
@@ -487,7 +516,7 @@ __global__ __launch_bounds__(XP_NT) void k_xpass(const cpx<R>* src, cpx<R>* dst,
 _Pragma("clang loop unroll(full)")
   for (int j = 0; j < PER; ++j) {
     const int e = min(tid + j * XP_NT, NX * TC - 1);
-    const cpx<R> q = src[bbase + size_t(t0) * TC + size_t(e / TC) * NYZ + (e % TC)];
+    const cpx<R> q = ld_stream<M>(&src[bbase + size_t(t0) * TC + size_t(e / TC) * NYZ + (e % TC)]);
     vx[j] = q.x;
     vy[j] = q.y;
   }
@@ -504,7 +533,7 @@ _Pragma("clang loop unroll(full)")
 _Pragma("clang loop unroll(full)")
       for (int j = 0; j < PER; ++j) {
         const int e = min(tid + j * XP_NT, NX * TC - 1);
-        const cpx<R> q = src[bbase + size_t(q0 + TC) + size_t(e / TC) * NYZ + (e % TC)];
+        const cpx<R> q = ld_stream<M>(&src[bbase + size_t(q0 + TC) + size_t(e / TC) * NYZ + (e % TC)]);
         vx[j] = q.x;
         vy[j] = q.y;
       }
@@ -526,7 +555,7 @@ _Pragma("clang loop unroll(full)")
 _Pragma("clang loop unroll(full)")
     for (int j = 0; j < PER; ++j) {
       const int e = tid + j * XP_NT;
-      if (e < NX * TC) dst[bbase + size_t(q0) + size_t(e / TC) * NYZ + (e % TC)] = tile[e];
+      if (e < NX * TC) st_stream<M>(&dst[bbase + size_t(q0) + size_t(e / TC) * NYZ + (e % TC)], tile[e]);
     }
     __syncthreads();
   }
@@ -1127,30 +1156,36 @@ static hipError_t set_lds(K kern, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
+template <typename R, int A, int B, int M>
+static hipError_t launch_plane_stage_m(int S, int NX, const StageArgs<R>& a, const ProjTables& pt,
+                                       const void* twy, const void* twz, hipStream_t st) {
+  const unsigned grid = unsigned(S) * unsigned(NX);
+  const auto ty = reinterpret_cast<const cpx<R>*>(twy);
+  const auto tz = reinterpret_cast<const cpx<R>*>(twz);
+  if constexpr (plane2_fits<R, A, B>()) {
+    constexpr size_t lds2 = plane2_lds_bytes<A, B>(sizeof(cpx<R>));
+    auto kern2 = k_plane_stage2<R, A, B, M>;
+    hipError_t e2 = set_lds(kern2, lds2);
+    if (e2 != hipSuccess) return e2;
+    hipLaunchKernelGGL(kern2, dim3(grid), dim3(2 * plane2_nth<R>(A * B)), lds2, st, a, pt, ty, tz, S, NX);
+  } else {
+    constexpr size_t lds = plane_lds_bytes<A, B>(sizeof(cpx<R>));
+    auto kern = k_plane_stage<R, A, B, M>;
+    hipError_t e = set_lds(kern, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(plane_nt(A * B)), lds, st, a, pt, ty, tz, S, NX);
+  }
+  return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_plane_stage(const int n[3], int S, const StageArgs<R>& a, const ProjTables& pt,
                               const void* twy, const void* twz, hipStream_t st) {
-  const unsigned grid = unsigned(S) * unsigned(n[0]);
-#define X(A, B)                                                                             \
-  if (n[1] == A && n[2] == B) {                                                             \
-    if constexpr (plane2_fits<R, A, B>()) {                                                 \
-      constexpr size_t lds2 = plane2_lds_bytes<A, B>(sizeof(cpx<R>));                       \
-      auto kern2 = k_plane_stage2<R, A, B>;                                                 \
-      hipError_t e2 = set_lds(kern2, lds2);                                                 \
-      if (e2 != hipSuccess) return e2;                                                      \
-      hipLaunchKernelGGL(kern2, dim3(grid), dim3(2 * plane2_nth<R>(A * B)), lds2, st, a, pt,   \
-                         reinterpret_cast<const cpx<R>*>(twy), reinterpret_cast<const cpx<R>*>(twz), \
-                         S, n[0]);                                                          \
-      return hipGetLastError();                                                             \
-    }                                                                                       \
-    constexpr size_t lds = plane_lds_bytes<A, B>(sizeof(cpx<R>));                           \
-    auto kern = k_plane_stage<R, A, B>;                                                     \
-    hipError_t e = set_lds(kern, lds);                                                      \
-    if (e != hipSuccess) return e;                                                          \
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(plane_nt(A * B)), lds, st, a, pt,             \
-                       reinterpret_cast<const cpx<R>*>(twy), reinterpret_cast<const cpx<R>*>(twz), \
-                       S, n[0]);                                                            \
-    return hipGetLastError();                                                               \
+#define X(A, B)                                                                              \
+  if (n[1] == A && n[2] == B) {                                                              \
+    if (a.cache_mode >= 2) return launch_plane_stage_m<R, A, B, 2>(S, n[0], a, pt, twy, twz, st); \
+    if (a.cache_mode == 1) return launch_plane_stage_m<R, A, B, 1>(S, n[0], a, pt, twy, twz, st); \
+    return launch_plane_stage_m<R, A, B, 0>(S, n[0], a, pt, twy, twz, st);                  \
   }
   NCT_PLANE_PAIRS(X)
 #undef X
@@ -1204,28 +1239,34 @@ hipError_t launch_plane_inv(const int n[3], int B, const void* in, void* out, R 
 
 template <typename R, int NX, int TC>
 static hipError_t launch_xpass_tc(int B, int NYZ, const void* src, void* dst, const R* g2x, const R* g2yz,
-                                  R kscale, int mode, const void* twx, hipStream_t st) {
+                                  R kscale, int mode, const void* twx, int cache_mode, hipStream_t st) {
   const int tiles = NYZ / TC;
   const auto s_ = reinterpret_cast<const cpx<R>*>(src);
   const auto d_ = reinterpret_cast<cpx<R>*>(dst);
   const auto t_ = reinterpret_cast<const cpx<R>*>(twx);
   // one tile per workgroup: prefetching a second tile (XT > 1) measured no faster on MI355X and
   // costs occupancy
-  hipLaunchKernelGGL((k_xpass<R, NX, TC, 1>), dim3(unsigned(B) * unsigned(tiles)), dim3(XP_NT), 0, st,
-                     s_, d_, NYZ, g2x, g2yz, kscale, mode, t_);
+  const dim3 grid(unsigned(B) * unsigned(tiles));
+  if (cache_mode >= 2)
+    hipLaunchKernelGGL((k_xpass<R, NX, TC, 1, 2>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_);
+  else if (cache_mode == 1)
+    hipLaunchKernelGGL((k_xpass<R, NX, TC, 1, 1>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_);
+  else
+    hipLaunchKernelGGL((k_xpass<R, NX, TC, 1, 0>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_);
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_xpass(const int n[3], int B, const void* src, void* dst, const R* g2x,
-                        const R* g2yz, R kscale, int mode, const void* twx, hipStream_t st) {
+                        const R* g2yz, R kscale, int mode, const void* twx, hipStream_t st,
+                        int cache_mode) {
   const int NYZ = n[1] * n[2];
 #define X(A)                                                                                \
   if (n[0] == A) {                                                                          \
     constexpr int TCP = xpass_tc<R>(A);                                                     \
     if (NYZ % TCP == 0)                                                                     \
-      return launch_xpass_tc<R, A, TCP>(B, NYZ, src, dst, g2x, g2yz, kscale, mode, twx, st); \
-    return launch_xpass_tc<R, A, 16>(B, NYZ, src, dst, g2x, g2yz, kscale, mode, twx, st);   \
+      return launch_xpass_tc<R, A, TCP>(B, NYZ, src, dst, g2x, g2yz, kscale, mode, twx, cache_mode, st); \
+    return launch_xpass_tc<R, A, 16>(B, NYZ, src, dst, g2x, g2yz, kscale, mode, twx, cache_mode, st); \
   }
   NCT_LINES(X)
 #undef X
@@ -1399,7 +1440,7 @@ hipError_t launch_real_to_cpx(const double* r, size_t N, void* out, hipStream_t 
   template hipError_t launch_plane_inv<R>(const int*, int, const void*, void*, R, const void*,     \
                                           const void*, hipStream_t);                               \
   template hipError_t launch_xpass<R>(const int*, int, const void*, void*, const R*, const R*, R,  \
-                                      int, const void*, hipStream_t);                              \
+                                      int, const void*, hipStream_t, int);                         \
   template hipError_t launch_xpass_energy<R>(const int*, int, const void*, const R*, const R*, R,  \
                                              const void*, double*, int*, hipStream_t);             \
   template hipError_t launch_density<R>(const void*, const double*, int, size_t, double*,          \
