@@ -17,6 +17,7 @@ Sources (paper arXiv 2506.21908, "Spin non-collinear real-time TDDFT ... INQ"):
   * Zeeman term mu_B sigma.b_ext                 Eq. (zeeman_potential), Sec. 3.4
   * Kleinman-Bylander + spin-orbit projectors    Eqs. (Vps), (Vps-soc), spinor harmonics, Sec. 3.5
   * Hartree potential                            Eq. (KSpot)
+  * uniform electric (laser) pulse               Sec. 4.7, pulse profile of Figs. (fe2-laser), (fe6-laser)
 The paper names no propagator, Taylor order, Poisson solver or LDA
 parametrisation; the readings taken here are listed in the design doc and below:
   * propagator: enforced time-reversal symmetry (ETRS) with a truncated Taylor
@@ -26,7 +27,10 @@ parametrisation; the readings taken here are listed in the design doc and below:
     b_xc = 0 where |m| < threshold;
   * Hartree: FFT Poisson solve with the G = 0 term dropped;
   * projectors: radial form r^l exp(-r^2/2rc^2) cut at r_sphere, normalised by
-    the continuum radial integral; channel energies absorb the KB denominator.
+    the continuum radial integral; channel energies absorb the KB denominator;
+  * laser: length gauge for an isolated system, v_E(r, t) = E(t).(r - c) with c the
+    cell centre (potential energy of a charge -1 in the field E), evaluated like
+    B(t): at t_n for H_n and t_{n+1} for H~; its energy int v_E n is part of E_loc.
 """
 from __future__ import annotations
 
@@ -222,6 +226,43 @@ class FieldSpec:
         return out
 
 
+@dataclass
+class LaserPulseSpec:
+    A: float
+    omega: float
+    t0: float
+    tau: float
+    phase: float = 0.0
+    pol: tuple = (0.0, 0.0, 1.0)
+
+
+@dataclass
+class LaserSpec:
+    """Uniform electric field E(t) = sum_k A_k pol_k cos(omega_k t + phase_k)
+    exp(-(t - t0_k)^2 / (2 tau_k^2))  (pulse profile of the optical runs, Sec. 4.7)."""
+    pulses: List[LaserPulseSpec] = field(default_factory=list)
+
+    def E(self, t: float) -> np.ndarray:
+        out = np.zeros(3)
+        for p in self.pulses:
+            g = math.exp(-(t - p.t0) ** 2 / (2.0 * p.tau * p.tau))
+            out = out + p.A * math.cos(p.omega * t + p.phase) * g * np.array(p.pol, dtype=np.float64)
+        return out
+
+
+def laser_potential(grid: "Grid", E: np.ndarray) -> np.ndarray:
+    """v_E(r) = E.(r - c): length-gauge potential energy of an electron (charge -1) in the uniform
+    field E, with r the grid point i*h and c the cell centre (the jump of this sawtooth sits on
+    the cell faces, where an isolated system has no density)."""
+    v = np.zeros(grid.n)
+    for d in range(3):
+        x = grid.axis(d) - 0.5 * grid.L[d]
+        sh = [1, 1, 1]
+        sh[d] = grid.n[d]
+        v = v + E[d] * x.reshape(sh)
+    return v
+
+
 # ----------------------------------------------------------------------------
 # spinor spherical harmonics and projectors (Sec. 3.5)
 # ----------------------------------------------------------------------------
@@ -369,6 +410,7 @@ class System:
     thr: float = 1e-12
     dt: float = 0.05
     K: int = 4
+    laser: LaserSpec = field(default_factory=LaserSpec)
 
 
 @dataclass
@@ -382,10 +424,12 @@ class Fields:
     n: np.ndarray
     m: np.ndarray
     B: np.ndarray
+    vE: np.ndarray = None  # laser potential at t (zeros without a laser)
 
 
 def fields_from_density(sysd: System, rho_v: np.ndarray, t: float) -> Fields:
-    """v = v_ext + v_H[n] + vbar_xc[n, m];  b = b_xc[n, m] + mu_B B(t)  (Eq. HNC-SDFT and its b_s)."""
+    """v = v_ext + v_E(t) + v_H[n] + vbar_xc[n, m];  b = b_xc[n, m] + mu_B B(t)  (Eq. HNC-SDFT and
+    its b_s; v_E the laser potential, zero without a laser)."""
     n, m = charge_and_magnetization(rho_v)
     grid = sysd.grid
     vH = hartree(n, grid) if sysd.hartree else np.zeros_like(n)
@@ -394,9 +438,10 @@ def fields_from_density(sysd: System, rho_v: np.ndarray, t: float) -> Fields:
     else:
         vbar, bxc, ex = np.zeros_like(n), np.zeros_like(m), np.zeros_like(n)
     B = sysd.bfield.B(t)
-    v = sysd.v_ext + vH + vbar
+    vE = laser_potential(grid, sysd.laser.E(t))
+    v = sysd.v_ext + vE + vH + vbar
     b = bxc + MU_B * B[:, None, None, None]
-    return Fields(v, b, vH, vbar, bxc, ex, n, m, B)
+    return Fields(v, b, vH, vbar, bxc, ex, n, m, B, vE)
 
 
 def apply_hamiltonian(sysd: System, psi: np.ndarray, F: Fields) -> np.ndarray:
@@ -447,7 +492,7 @@ OBS_NAMES = ["t", "N_e", "M_x", "M_y", "M_z", "E_total", "E_kin", "E_loc", "E_NL
 def observables(sysd: System, psi: np.ndarray, t: float) -> np.ndarray:
     """Row of 13 doubles: t, N_e, M, energies and the largest |<psi_i|psi_i> - 1|.
 
-    E = sum_i f_i <psi_i|T|psi_i> + int v_ext n + sum_i f_i sum_p E_p |C_p,i|^2
+    E = sum_i f_i <psi_i|T|psi_i> + int (v_ext + v_E(t)) n + sum_i f_i sum_p E_p |C_p,i|^2
         + mu_B B.M + 1/2 int v_H n + int e_x.
     """
     grid = sysd.grid
@@ -460,7 +505,7 @@ def observables(sysd: System, psi: np.ndarray, t: float) -> np.ndarray:
     f = sysd.occ
     Tpsi = kinetic(psi, grid)
     ekin = float(np.sum(f * np.real(np.sum(psi.conj() * Tpsi, axis=(1, 2, 3, 4)))) * dV)
-    eloc = float(np.sum(sysd.v_ext * n) * dV)
+    eloc = float(np.sum((sysd.v_ext + F.vE) * n) * dV)
     enl = 0.0
     if sysd.projs:
         for ap, C in zip(sysd.projs, projections(psi, sysd.projs, grid)):
@@ -581,6 +626,8 @@ def system_from_workload(w, dt: Optional[float] = None) -> System:
     bf = FieldSpec(tuple(w.bfield.B0),
                    [PulseSpec(p.A, p.omega, p.t0, p.tau, p.phase, tuple(p.e1), tuple(p.e2))
                     for p in w.bfield.pulses])
+    laser = LaserSpec([LaserPulseSpec(p.A, p.omega, p.t0, p.tau, p.phase, tuple(p.pol))
+                       for p in getattr(w, "laser", [])])
     return System(grid=grid, occ=np.asarray(w.occ, dtype=np.float64), v_ext=w.v_ext,
                   projs=projs, bfield=bf, xc=w.xc, hartree=w.hartree, thr=w.m_threshold,
-                  dt=w.dt if dt is None else dt, K=w.taylor_order)
+                  dt=w.dt if dt is None else dt, K=w.taylor_order, laser=laser)

@@ -70,6 +70,25 @@ class BField:
 
 
 @dataclasses.dataclass
+class LaserPulse:
+    """Uniform electric pulse (optical excitation, magnetic component neglected).
+
+    E(t) = A pol cos(omega t + phase) exp(-(t-t0)^2 / (2 tau^2))
+    """
+    A: float
+    omega: float
+    t0: float
+    tau: float
+    phase: float = 0.0
+    pol: Tuple[float, float, float] = (0.0, 0.0, 1.0)
+
+
+# unit conversions for the laser parameters quoted in eV and fs
+EV_HA = 1.0 / 27.211386245988
+FS_AU = 41.341373335
+
+
+@dataclasses.dataclass
 class Workload:
     name: str
     n: Tuple[int, int, int]
@@ -91,6 +110,7 @@ class Workload:
     m_threshold: float = 1e-12
     taylor_order: int = 4
     checkpoint_every: int = 0
+    laser: List[LaserPulse] = dataclasses.field(default_factory=list)
 
     @property
     def natoms(self) -> int:
@@ -196,6 +216,49 @@ def tilted_product_spinors(rng, S: int, n, L, tilt_deg: float = 30.0) -> np.ndar
     return psi
 
 
+def localized_product_spinors(rng, S: int, n, L, sigma_env: float, tilt_deg: float = 30.0) -> np.ndarray:
+    """Like tilted_product_spinors, with every orbital multiplied by a Gaussian envelope of width
+    sigma_env about the cell centre before orthonormalisation: a cluster isolated in its box."""
+    N = int(np.prod(n))
+    dV = float(np.prod(L)) / N
+    env = np.ones(tuple(n))
+    for d in range(3):
+        x = np.arange(n[d]) * (L[d] / n[d]) - 0.5 * L[d]
+        sh = [1, 1, 1]
+        sh[d] = n[d]
+        env = env * np.exp(-0.5 * (x / sigma_env) ** 2).reshape(sh)
+    z = (_smooth_noise(rng, S, n, L) * env[None]).reshape(S, N)
+    phi = _orthonormal_columns(z, dV).reshape((S,) + tuple(n))
+    h = math.radians(tilt_deg) / 2.0
+    chi_p = np.array([math.cos(h), math.sin(h)])
+    chi_m = np.array([-math.sin(h), math.cos(h)])
+    nplus = (3 * S + 3) // 4
+    psi = np.empty((S, 2) + tuple(n), dtype=np.complex128)
+    for i in range(S):
+        chi = chi_p if i < nplus else chi_m
+        psi[i, 0] = chi[0] * phi[i]
+        psi[i, 1] = chi[1] * phi[i]
+    return psi
+
+
+def central_positions(rng, natoms: int, L, radius: float, min_sep: float) -> np.ndarray:
+    """Atoms uniform in a ball of the given radius about the cell centre, pairwise >= min_sep."""
+    c = 0.5 * np.asarray(L, dtype=np.float64)
+    pos: List[np.ndarray] = []
+    tries = 0
+    while len(pos) < natoms:
+        tries += 1
+        if tries > 100000:
+            raise RuntimeError("could not place atoms with the requested separation")
+        u = rng.uniform(-1.0, 1.0, 3)
+        if np.dot(u, u) > 1.0:
+            continue
+        p = c + radius * u
+        if all(np.linalg.norm(p - q) >= min_sep for q in pos):
+            pos.append(p)
+    return np.array(pos).reshape(natoms, 3)
+
+
 def separated_positions(rng, natoms: int, L, min_sep: float = 5.0) -> np.ndarray:
     L = np.asarray(L, dtype=np.float64)
     pos: List[np.ndarray] = []
@@ -238,12 +301,16 @@ def make_system(n=(8, 8, 8), L=(6.0, 6.0, 6.0), nstates=4, natoms=0, case=7,
                 projectors=True, lambda_so=0.05, r_sphere=2.5, rc=0.7,
                 full_spinors=True, bfield: Optional[BField] = None, dt=0.05,
                 nsteps=4, xc=1, hartree=1, min_sep=None, name="custom",
-                depth_range=(1.0, 3.0), width=1.0, taylor_order=4) -> Workload:
+                depth_range=(1.0, 3.0), width=1.0, taylor_order=4,
+                laser: Optional[List[LaserPulse]] = None, localized: Optional[float] = None) -> Workload:
     """A seeded system of arbitrary (small) shape, for tests."""
     r_pos, r_depth, r_states, _ = _rngs(case)
     n = tuple(int(v) for v in n)
     L = tuple(float(v) for v in L)
-    if natoms > 0:
+    if natoms > 0 and localized is not None:
+        sep = min_sep if min_sep is not None else min(4.2, 0.3 * min(L))
+        pos = central_positions(r_pos, natoms, L, 0.2 * min(L), sep)
+    elif natoms > 0:
         sep = min_sep if min_sep is not None else min(5.0, 0.45 * min(L))
         pos = separated_positions(r_pos, natoms, L, sep)
     else:
@@ -251,7 +318,9 @@ def make_system(n=(8, 8, 8), L=(6.0, 6.0, 6.0), nstates=4, natoms=0, case=7,
     depths = r_depth.uniform(depth_range[0], depth_range[1], max(natoms, 0))
     widths = np.full(max(natoms, 0), width)
     v_ext = gaussian_local_potential(n, L, pos, depths, widths)
-    if full_spinors:
+    if localized is not None:
+        psi0 = localized_product_spinors(r_states, nstates, n, L, localized)
+    elif full_spinors:
         psi0 = random_spinors_full(r_states, nstates, n, L)
     else:
         psi0 = tilted_product_spinors(r_states, nstates, n, L)
@@ -261,7 +330,7 @@ def make_system(n=(8, 8, 8), L=(6.0, 6.0, 6.0), nstates=4, natoms=0, case=7,
                     channels=chans, r_sphere=r_sphere, psi0=psi0,
                     bfield=bfield if bfield is not None else BField(),
                     dt=dt, nsteps=nsteps, xc=xc, hartree=hartree,
-                    taylor_order=taylor_order)
+                    taylor_order=taylor_order, laser=list(laser) if laser else [])
 
 
 def workload(case: int) -> Workload:
@@ -272,8 +341,22 @@ def workload(case: int) -> Workload:
     2 solid-like 64^3 x 256, 16 atoms bcc 2x2x2 (+0.05 bohr jitter), circular pulse, 1000 steps
     3 gradient case 32^3 x 32, 2 atoms, 4 circular pulse components, 200 steps, checkpoint 20
     4 large 96^3 x 512, 32 atoms, 4 circular pulse components, 500 steps, checkpoint 25
+    5 laser-driven cluster 48^3 x 64, 4 atoms within 5 bohr of the centre, states in a Gaussian
+      envelope (sigma 3.5 bohr) about the centre, z-polarised electric pulse A = 1 a.u.,
+      omega = 10 eV, t0 = 0.1 fs, tau = 0.5 fs (the parameters of the paper's cluster runs),
+      200 steps
     """
     r_pos, r_depth, r_states, _r_jit = _rngs(case)
+    if case == 5:
+        n, L, S, natoms = (48, 48, 48), (20.0,) * 3, 64, 4
+        pos = central_positions(r_pos, natoms, L, 5.0, 4.2)
+        depths = r_depth.uniform(1.0, 3.0, natoms)
+        widths = np.ones(natoms)
+        v_ext = gaussian_local_potential(n, L, pos, depths, widths)
+        psi0 = localized_product_spinors(r_states, S, n, L, 3.5)
+        laser = [LaserPulse(A=1.0, omega=10.0 * EV_HA, t0=0.1 * FS_AU, tau=0.5 * FS_AU)]
+        return Workload("laser-cluster-48^3x64-4x18KB", n, L, S, np.ones(S), pos, depths, widths,
+                        v_ext, kb_channels(), 2.5, psi0, BField(), 0.05, 200, laser=laser)
     if case == 0:
         n, L, S, natoms = (16, 16, 16), (10.0,) * 3, 8, 4
         pos = separated_positions(r_pos, natoms, L, 2.0)

@@ -551,6 +551,55 @@ def test_charge_conserved_and_collinear_limit():
     assert np.allclose(obs[:, 2:4], 0, atol=1e-14)
 
 
+# ---------------------------------------------------------------- laser (Sec. 4.7)
+def _laser_packet_system(dt, E0):
+    grid = O.Grid((28, 28, 40), (14.0, 14.0, 20.0))   # packet tails negligible at the faces
+    sysd = _free_system(grid.n, grid.L, dt=dt)
+    sysd.laser = O.LaserSpec([O.LaserPulseSpec(A=E0, omega=0.0, t0=0.0, tau=1e9, pol=(0.0, 0.0, 1.0))])
+    X, Y, Z = np.meshgrid(grid.axis(0), grid.axis(1), grid.axis(2), indexing="ij")
+    c = [grid.L[d] / 2 for d in range(3)]
+    g = np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) / 2.0)
+    g = g / math.sqrt(np.sum(g * g) * grid.dV)
+    psi = np.stack([g, 0 * g])[None].astype(complex)
+    return sysd, psi, (X - c[0], Y - c[1], Z - c[2])
+
+
+def test_laser_ehrenfest_uniform_acceleration():
+    """A packet at rest in a static uniform field: for a linear potential Ehrenfest's theorem is
+    exact, so <r> - c = -E t^2/2 (force -E on a charge -1); pins the sign and size of v_E."""
+    E0, T = 0.5, 1.2
+    sysd, psi, rel = _laser_packet_system(0.04, E0)
+    p, obs = O.run(sysd, psi, 30)
+    n, _ = O.charge_and_magnetization(O.spin_density(p, sysd.occ))
+    dV = sysd.grid.dV
+    disp = [float(np.sum(n * r) * dV) for r in rel]
+    assert abs(disp[2] + 0.5 * E0 * T * T) < 1e-6
+    # transverse: zero but for the packet tail on the unpaired face point x - c = -L/2
+    assert abs(disp[0]) < 1e-7 and abs(disp[1]) < 1e-7
+    # the energy includes int v_E n: conserved while kinetic energy grows by E^2 T^2/2
+    assert abs(obs[-1, 5] - obs[0, 5]) < 1e-6
+    assert abs(obs[-1, 6] - obs[0, 6] - 0.5 * E0 * E0 * T * T) < 1e-5
+    assert abs(obs[-1, 7] - E0 * disp[2]) < 1e-12
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.05])
+def test_laser_rotates_magnetisation_only_through_soc(lam):
+    """Without spin-orbit coupling the electric pulse acts on the charge only: the collinear
+    product states keep M along its initial direction (to rounding; |M| follows the Taylor norm
+    error).  With SOC the pulse turns M (Sec. 4.7, Eq. SOtorque)."""
+    las = [I.LaserPulse(A=0.5, omega=0.4, t0=0.3, tau=0.3, pol=(0.0, 0.0, 1.0))]
+    w = I.make_system(n=(12, 12, 12), L=(9.0,) * 3, nstates=3, natoms=2, case=41, lambda_so=lam,
+                      dt=0.05, laser=las, localized=1.8, full_spinors=False)
+    sysd = O.system_from_workload(w)
+    _, obs = O.run(sysd, w.psi0, 12)
+    n0 = obs[0, 2:5] / np.linalg.norm(obs[0, 2:5])
+    perp = max(np.linalg.norm(np.cross(row[2:5], n0)) for row in obs)
+    if lam == 0.0:
+        assert perp < 1e-13
+    else:
+        assert perp > 1e-4
+
+
 # ---------------------------------------------------------------- gradient oracle
 def test_tangent_linear_gradient_matches_central_differences():
     bf = I.BField(pulses=I.circular_pulses([0.1, 0.2], [0.5, 1.0], 0.05, 0.1))
