@@ -1,6 +1,6 @@
 """Benchmark: ETRS steps/s of the non-collinear TDDFT step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cluster|solid|tiny|grad]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cluster|solid|tiny|grad|large|laser]
                 [--precision fp64|mixed] [--no-cpu-baseline] [--copy-probe]
 
 Times exactly K ETRS steps (after W untimed warm-up steps) of the magnetic-cluster-like
@@ -21,9 +21,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "TDDFT steps/s + Hψ HBM GB/s, FP64 vs FP32-mixed; adjoint/forward time ratio"
 HBM_PEAK_GBS = 8000.0
-WORKLOADS = {"tiny": 0, "cluster": 1, "solid": 2, "grad": 3, "large": 4}
+WORKLOADS = {"tiny": 0, "cluster": 1, "solid": 2, "grad": 3, "large": 4, "laser": 5}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2506_21908_amd", "csrc", "nct_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "plane_stage_cluster48_fp64_traffic.md")
+
+
+def dataclass_dict(p) -> dict:
+    return {k: (list(v) if isinstance(v, tuple) else v) for k, v in vars(p).items()}
 
 
 def kernel_hash() -> str:
@@ -170,6 +174,7 @@ def main():
                    "projectors_per_atom": sum(c.twoj + 1 for c in w.channels),
                    "dt": w.dt, "taylor_order": w.taylor_order, "propagator": "ETRS",
                    "xc": "Slater exchange, locally collinear", "hartree": "FFT",
+                   "laser": [dataclass_dict(p) for p in w.laser] or None,
                    "precision": args.precision, "parallelism": "single GPU"},
         "roofline": {"kernel": "k_plane_stage (fused plane pass)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -17,6 +17,8 @@
  *   - Exchange-correlation: adiabatic, locally collinear, Eqs. (LC+ALDA2),
  *     (LC+ALDA); Slater exchange; b_xc = 0 where |m| < m_threshold.
  *   - Hartree: Eq. (KSpot) solved by FFT, G = 0 term dropped.
+ *   - Optional uniform electric (laser) pulse E(t) with the temporal profile of
+ *     the optical runs of Sec. 4.7, in the length gauge (see nct_set_laser).
  *   - Propagator (the paper names none): enforced time-reversal symmetry with
  *     a truncated Taylor exponential of order taylor_order:
  *        phi = T(-i dt/2 H[rho(psi_n), B(t_n)]) psi_n
@@ -132,6 +134,25 @@ void nct_destroy_system(nct_system *sys);
 /* Text of the last error on sys, or of the last nct_create_system failure when sys is NULL. */
 const char *nct_last_error(const nct_system *sys);
 
+/* Uniform electric pulse (Sec. 4.7; the magnetic component of the light is neglected):
+ * E(t) = A pol cos(omega t + phase) exp(-(t - t0)^2 / 2 tau^2), atomic units of field. */
+typedef struct {
+  double A, omega, t0, tau, phase;
+  double pol[3];
+} nct_laser_pulse;
+
+/* Set the uniform electric field E(t) = sum of the given pulses, acting on the charge in the
+ * length gauge: the local potential gains v_E(r, t) = E(t).(r - c) (potential energy of a charge
+ * -1), r = (ix hx, iy hy, iz hz), c = cell / 2.  The sawtooth jumps on the cell faces, so this
+ * describes an isolated system whose density vanishes there.  E is evaluated like B_ext: at t_n
+ * for H_n and at t_n + dt for H~.  int v_E n enters E_loc of the observables, and the fields
+ * returned by nct_get_fields include v_E(t).  Like B_ext it is not applied while the fields are
+ * frozen (nct_set_potentials with fields_dev).
+ *   pulses  host [npulses] (copied); npulses = 0 (pulses may be NULL) removes the field.
+ * Errors: NCT_ERR_ARG if npulses < 0, npulses > 0 with pulses NULL, or a pulse has tau <= 0 or
+ * a non-finite parameter. */
+nct_status nct_set_laser(nct_system *sys, int npulses, const nct_laser_pulse *pulses);
+
 /* Set the potentials of Eq. (HNC-SDFT):
  *   v_ext_dev  device double [N]: external local potential v_ext(r) (copied), or NULL to keep;
  *   b          host: B_ext(t) description (copied), or NULL to keep;
@@ -152,11 +173,11 @@ nct_status nct_density_magnetization(nct_system *sys, const void *psi_dev, doubl
                                      double *rho_v_dev, double *totals_host, int update_fields);
 
 /* Current total local fields at time t into device double [4][N] {v, b_x, b_y, b_z}
- * (v = v_ext + v_H + vbar_xc, b = b_xc + mu_B B_ext(t)). */
+ * (v = v_ext + v_E(t) + v_H + vbar_xc, b = b_xc + mu_B B_ext(t); v_E is zero without a laser). */
 nct_status nct_get_fields(nct_system *sys, double t, double *fields_dev);
 
-/* hpsi = H psi with the current fields and B_ext(t) (psi and hpsi distinct buffers of the
- * psi layout above). */
+/* hpsi = H psi with the current fields, B_ext(t) and v_E(t) (psi and hpsi distinct buffers of
+ * the psi layout above). */
 nct_status nct_apply_hamiltonian(nct_system *sys, const void *psi_dev, void *hpsi_dev, double t);
 
 /* Advance psi in place by nsteps ETRS steps from time t0.  The fields of the first step are

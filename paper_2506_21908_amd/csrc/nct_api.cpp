@@ -65,6 +65,7 @@ struct nct_system {
   std::vector<double> positions_h;
   std::vector<nct_channel> channels_h;
   std::vector<nct_pulse> pulses;
+  std::vector<nct_laser_pulse> laser;   // uniform electric pulses (length gauge)
   double B0[3] = {0, 0, 0};
   bool frozen = false;
   bool fields_valid = false;
@@ -86,8 +87,8 @@ struct nct_system {
   double* fields_scr = nullptr;
   float* fields32 = nullptr;
   void* ncpx = nullptr;        // complex double [N] Poisson work
-  double* fpart = nullptr;     // [nblk][8]
-  double* ftot = nullptr;      // [8]
+  double* fpart = nullptr;     // [nblk][kFieldTot]
+  double* ftot = nullptr;      // [kFieldTot]
   double* epart = nullptr;     // [2S][ntiles][2]
   double* obs_dev = nullptr;   // [cap][13]
   int obs_cap = 0;
@@ -487,6 +488,29 @@ void bfield_at(const nct_system* s, double t, double B[3]) {
   }
 }
 
+// Uniform electric field E(t) of the laser pulses (zero without pulses)
+void efield_at(const nct_system* s, double t, double E[3]) {
+  E[0] = E[1] = E[2] = 0.0;
+  for (const nct_laser_pulse& p : s->laser) {
+    const double d = t - p.t0;
+    const double g = std::exp(-d * d / (2 * p.tau * p.tau));
+    const double a = p.A * std::cos(p.omega * t + p.phase) * g;
+    for (int k = 0; k < 3; ++k) E[k] += a * p.pol[k];
+  }
+}
+
+// Length-gauge potential v_E = E.(r - c) at grid point (ix, iy, iz) as lg[0] ix + lg[1] iy +
+// lg[2] iz + lg[3]: lg[d] = E_d h_d, lg[3] = -E.c with c the cell centre.
+void laser_coeffs(const nct_system* s, double t, double lg[4]) {
+  double E[3];
+  efield_at(s, t, E);
+  lg[3] = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    lg[d] = E[d] * (s->prm.cell[d] / s->n[d]);
+    lg[3] -= E[d] * 0.5 * s->prm.cell[d];
+  }
+}
+
 // d B / d theta, theta = (A_1..A_k, omega_1..omega_k); out [2k][3]
 void bfield_jac(const nct_system* s, double t, std::vector<double>& out) {
   const size_t k = s->pulses.size();
@@ -549,9 +573,9 @@ struct Engine {
     double* out = store ? s->fields : s->fields_scr;
     float* o32 = (store && !s->fp64) ? s->fields32 : nullptr;
     if ((r = check(timed(s, K, (32 + 16 + 32 + (o32 ? 16 : 0)) * N, 0, [&] {
-           return launch_fields(s->rho, s->vext, vh, s->prm.xc, s->prm.m_threshold, s->N, out, o32,
+           return launch_fields(s->rho, s->vext, vh, s->prm.xc, s->prm.m_threshold, s->n, s->prm.cell, out, o32,
                                 s->fpart, &nb, s->st); }), "fields")) != NCT_OK) return r;
-    if ((r = check(timed(s, K, 64.0 * nb, 0, [&] { return launch_reduce_rows(s->fpart, nb, 8, s->ftot, s->st); }),
+    if ((r = check(timed(s, K, 8.0 * kFieldTot * nb, 0, [&] { return launch_reduce_rows(s->fpart, nb, kFieldTot, s->ftot, s->st); }),
                    "reduce")) != NCT_OK) return r;
     if (store) s->fields_valid = true;
     return NCT_OK;
@@ -591,6 +615,14 @@ struct Engine {
     if (s->natoms == 0) return NCT_OK;
     HIPCHK(s, hipStreamWaitEvent(s->st, s->ev_proj, 0));
     return NCT_OK;
+  }
+
+  // external fields of a plane-pass stage at time t: mu_B B_ext(t) and the laser potential
+  void externals(double t, StageArgs<R>& sa) {
+    bext_now(t, sa.bext);
+    double lg[4] = {0, 0, 0, 0};
+    if (!s->frozen && !s->laser.empty()) laser_coeffs(s, t, lg);
+    for (int k = 0; k < 4; ++k) sa.lg[k] = R(lg[k]);
   }
 
   void bext_now(double t, R out[3]) {
@@ -732,7 +764,7 @@ struct Engine {
     const void* cW = xW;
     StageArgs<R> sa;
     sa.cache_mode = s->cache_mode;
-    bext_now(t, sa.bext);
+    externals(t, sa);
     sa.fields = fieldsR();
     nct_status r;
     Group G[2];
@@ -794,9 +826,15 @@ struct Engine {
     in.dV = s->dV;
     in.invN = 1.0 / double(s->N);
     in.t = t;
-    double B[3] = {0, 0, 0};
-    if (!s->frozen) bfield_at(s, t, B);
-    for (int k = 0; k < 3; ++k) in.muB_B[k] = kMuB * B[k];
+    double B[3] = {0, 0, 0}, E[3] = {0, 0, 0};
+    if (!s->frozen) {
+      bfield_at(s, t, B);
+      efield_at(s, t, E);
+    }
+    for (int k = 0; k < 3; ++k) {
+      in.muB_B[k] = kMuB * B[k];
+      in.efield[k] = E[k];
+    }
     return check(timed(s, NCT_K_OBS, 0, 0, [&] { return launch_obs_row(in, row, s->st); }), "obs_row");
   }
 
@@ -924,7 +962,7 @@ struct Engine {
     if ((r = prepare(lam_out, s->tmp, s->Wwork)) != NCT_OK) return r;
     StageArgs<R> sa;
     sa.cache_mode = s->cache_mode;
-    bext_now(t, sa.bext);
+    externals(t, sa);
     sa.fields = fieldsR();
     const void* cur = lam_out;
     for (int k = K; k >= 1; --k) {
@@ -1051,7 +1089,7 @@ struct Engine {
     if ((r = join_projections()) != NCT_OK) return r;
     StageArgs<R> sa;
     sa.cache_mode = s->cache_mode;
-    bext_now(t, sa.bext);
+    externals(t, sa);
     sa.fields = fieldsR();
     sa.tmp_in = s->tmp;
     sa.w_in = psi;
@@ -1231,9 +1269,9 @@ nct_status create_impl(const nct_params* p, nct_system** out) {
   if ((r = dalloc(s, 4 * N * 4, &p0)) != NCT_OK) return bail(r);
   s->fields32 = (float*)p0;
   if ((r = dalloc(s, N * 16, &s->ncpx)) != NCT_OK) return bail(r);
-  if ((r = dalloc(s, ((N + 255) / 256) * 8 * 8, &p0)) != NCT_OK) return bail(r);
+  if ((r = dalloc(s, ((N + 255) / 256) * kFieldTot * 8, &p0)) != NCT_OK) return bail(r);
   s->fpart = (double*)p0;
-  if ((r = dalloc(s, 8 * 8, &p0)) != NCT_OK) return bail(r);
+  if ((r = dalloc(s, kFieldTot * 8, &p0)) != NCT_OK) return bail(r);
   s->ftot = (double*)p0;
   const size_t nyz = size_t(p->n[1]) * p->n[2];
   if ((r = dalloc(s, size_t(2 * s->S) * (nyz / 16) * 2 * 8, &p0)) != NCT_OK) return bail(r);
@@ -1324,6 +1362,21 @@ const char* nct_last_error(const nct_system* sys) {
   return sys ? sys->err.c_str() : g_create_error.c_str();
 }
 
+nct_status nct_set_laser(nct_system* s, int npulses, const nct_laser_pulse* pulses) {
+  if (!s) return NCT_ERR_ARG;
+  if (npulses < 0) return fail(s, NCT_ERR_ARG, "npulses < 0");
+  if (npulses > 0 && !pulses) return fail(s, NCT_ERR_ARG, "pulses is NULL");
+  for (int k = 0; k < npulses; ++k) {
+    const nct_laser_pulse& p = pulses[k];
+    const double v[8] = {p.A, p.omega, p.t0, p.tau, p.phase, p.pol[0], p.pol[1], p.pol[2]};
+    for (double x : v)
+      if (!std::isfinite(x)) return fail(s, NCT_ERR_ARG, "laser pulse %d: non-finite parameter", k);
+    if (!(p.tau > 0)) return fail(s, NCT_ERR_ARG, "laser pulse %d: tau must be > 0", k);
+  }
+  s->laser.assign(pulses, pulses + npulses);
+  return NCT_OK;
+}
+
 nct_status nct_set_potentials(nct_system* s, const double* v_ext_dev, const nct_bfield* b,
                               const double* fields_dev) {
   if (!s) return NCT_ERR_ARG;
@@ -1380,12 +1433,13 @@ nct_status nct_density_magnetization(nct_system* s, const void* psi, double t, d
 nct_status nct_get_fields(nct_system* s, double t, double* out) {
   if (!s || !out) return s ? fail(s, NCT_ERR_ARG, "out is NULL") : NCT_ERR_ARG;
   if (!s->fields_valid) return fail(s, NCT_ERR_STATE, "fields not computed yet");
-  double B[3] = {0, 0, 0};
+  double B[3] = {0, 0, 0}, lg[4] = {0, 0, 0, 0};
   if (!s->frozen) {
     bfield_at(s, t, B);
     for (int k = 0; k < 3; ++k) B[k] *= kMuB;
+    if (!s->laser.empty()) laser_coeffs(s, t, lg);
   }
-  HIPCHK(s, launch_add_bext(s->fields, s->N, B, out, s->st));
+  HIPCHK(s, launch_add_bext(s->fields, s->n, B, lg, out, s->st));
   return NCT_OK;
 }
 

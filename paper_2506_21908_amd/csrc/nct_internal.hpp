@@ -38,6 +38,7 @@ struct StageArgs {
   void* w_out = nullptr;          // alpha x + c H w_in
   const R* fields = nullptr;      // [4][N] {v, b_x, b_y, b_z}
   R bext[3] = {0, 0, 0};          // mu_B B_ext added to b
+  R lg[4] = {0, 0, 0, 0};         // laser potential lg[0] ix + lg[1] iy + lg[2] iz + lg[3]
   R cre = 1, cim = 0;             // coefficient c of H w
   R alpha = 0;                    // coefficient of x_base
   const void* Y = nullptr;        // nonlocal scatter rows [S][2][Jtot], or null
@@ -80,16 +81,21 @@ hipError_t launch_density(const void* psi, const double* occ, int S, size_t N, d
                           hipStream_t st);
 
 // fields[4][N] = {v_ext + v_H + vbar, b_xc}; fields32 optional float copy;
-// part[nblk][8] = {N_e, M_x, M_y, M_z, E_loc, E_H, E_xc, 0} partial sums (not scaled by dV)
+// part[nblk][kFieldTot] partial sums (slots below)
+// Slots of the per-block field partial sums (not scaled by dV).
+constexpr int kFieldTot = 12;  // N_e, M_x, M_y, M_z, E_loc, E_H, E_xc, 0, D_x, D_y, D_z, 0
+// D = sum (r - c) n, r = (ix hx, iy hy, iz hz), c = cell / 2: the dipole that gives the laser
+// energy E.D dV.
 hipError_t launch_fields(const double* rho, const double* vext, const double* vH, int xc,
-                         double thr, size_t N, double* fields, float* fields32, double* part,
-                         int* nblk_out, hipStream_t st);
+                         double thr, const int n[3], const double cell[3], double* fields,
+                         float* fields32, double* part, int* nblk_out, hipStream_t st);
 hipError_t launch_reduce_rows(const double* part, int nrows, int width, double* out,
                               hipStream_t st);
 hipError_t launch_rho_to_n(const double* rho, size_t N, void* ncpx, hipStream_t st);
 hipError_t launch_cpx_real(const void* c, size_t N, double* out, hipStream_t st);
-hipError_t launch_add_bext(const double* fields, size_t N, const double b[3], double* out,
-                           hipStream_t st);
+// out = fields + {v_E, b}: v_E = lg[0] ix + lg[1] iy + lg[2] iz + lg[3] (laser), b added to b_xc
+hipError_t launch_add_bext(const double* fields, const int n[3], const double b[3],
+                           const double lg[4], double* out, hipStream_t st);
 hipError_t launch_to_float(const double* in, size_t n, float* out, hipStream_t st);
 
 // Projectors: C = dV beta^H W (per atom), EC = E * C; Y = beta EC.
@@ -111,6 +117,7 @@ struct ObsInputs {
   int S, natoms, PP, precision;
   double dV, invN, t;
   double muB_B[3];          // mu_B B_ext(t)
+  double efield[3];         // laser field E(t) (E_loc gains E.D dV)
 };
 hipError_t launch_obs_row(const ObsInputs& in, double* row, hipStream_t st);
 

@@ -128,12 +128,13 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a
   const cpx<R>* __restrict__ win = reinterpret_cast<const cpx<R>*>(a.w_in);
   const cpx<R>* __restrict__ xb = reinterpret_cast<const cpx<R>*>(a.x_base);
   const R* __restrict__ F = a.fields;
+  const R lx = a.lg[0] * R(x) + a.lg[3];  // laser potential of this plane, less its y, z terms
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
     const int e = tid + j * NT;
     if (e < NP) {
       const size_t p = size_t(x) * NP + e;
-      const R v = F[p];
+      const R v = F[p] + (lx + a.lg[1] * R(e / NZ) + a.lg[2] * R(e % NZ));
       const R bx = F[N + p] + a.bext[0];
       const R by = F[2 * N + p] + a.bext[1];
       const R bz = F[3 * N + p] + a.bext[2];
@@ -309,6 +310,7 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(Stag
     const cpx<R>* __restrict__ xb = reinterpret_cast<const cpx<R>*>(a.x_base);
     const bool xsep = xb && (a.x_base != a.w_in);
     const R* __restrict__ F = a.fields;
+    const R lx = a.lg[0] * R(x) + a.lg[3];  // laser potential of this plane, less its y, z terms
 #pragma unroll
     for (int j0 = 0; j0 < PPT; j0 += G) {
       cpx<R> wu[G], wd[G], xu[G], xd[G];
@@ -339,7 +341,8 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(Stag
         if (j0 + g < PPT && e < NP) {
           const int q = (e / NZ) * PZ + (e % NZ);
           const cpx<R> tu = planes[q], td = planes[PL + q];
-          const R v = fv[g], bx = fx[g] + a.bext[0], by = fy[g] + a.bext[1], bz = fz[g] + a.bext[2];
+          const R v = fv[g] + (lx + a.lg[1] * R(e / NZ) + a.lg[2] * R(e % NZ));
+          const R bx = fx[g] + a.bext[0], by = fy[g] + a.bext[1], bz = fz[g] + a.bext[2];
           cpx<R> hu, hd;
           hu.x = tu.x + (v + bz) * wu[g].x + bx * wd[g].x + by * wd[g].y;
           hu.y = tu.y + (v + bz) * wu[g].y + bx * wd[g].y - by * wd[g].x;
@@ -642,11 +645,13 @@ __global__ __launch_bounds__(256) void k_density(const cpx<R>* __restrict__ psi,
 __global__ __launch_bounds__(256) void k_fields(const double* __restrict__ rho,
                                                 const double* __restrict__ vext,
                                                 const double* __restrict__ vH, int xc, double thr,
-                                                size_t N, double* __restrict__ fields,
+                                                int ny, int nz, double hx, double hy, double hz,
+                                                double cx, double cy, double cz, size_t N,
+                                                double* __restrict__ fields,
                                                 float* __restrict__ f32, double* __restrict__ part) {
   __shared__ double red[4];
   const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
-  double n = 0, mx = 0, my = 0, mz = 0, eloc = 0, eh = 0, ex = 0;
+  double n = 0, mx = 0, my = 0, mz = 0, eloc = 0, eh = 0, ex = 0, dx = 0, dy = 0, dz = 0;
   if (p < N) {
     const double ruu = rho[p], rdd = rho[N + p], rr = rho[2 * N + p], ri = rho[3 * N + p];
     n = ruu + rdd;
@@ -686,14 +691,21 @@ __global__ __launch_bounds__(256) void k_fields(const double* __restrict__ rho,
     }
     eloc = ve * n;
     eh = 0.5 * vh * n;
+    const size_t nyz = size_t(ny) * nz;
+    const int ix = int(p / nyz);
+    const int rem = int(p - size_t(ix) * nyz);
+    const int iy = rem / nz;
+    const int iz = rem - iy * nz;
+    dx = (ix * hx - cx) * n;
+    dy = (iy * hy - cy) * n;
+    dz = (iz * hz - cz) * n;
   }
-  const double vals[7] = {n, mx, my, mz, eloc, eh, ex};
+  const double vals[kFieldTot] = {n, mx, my, mz, eloc, eh, ex, 0.0, dx, dy, dz, 0.0};
 #pragma unroll
-  for (int k = 0; k < 7; ++k) {
-    const double t = block_sum<256>(vals[k], red);
-    if (threadIdx.x == 0) part[size_t(blockIdx.x) * 8 + k] = t;
+  for (int k = 0; k < kFieldTot; ++k) {
+    const double t = (k == 7 || k == 11) ? 0.0 : block_sum<256>(vals[k], red);
+    if (threadIdx.x == 0) part[size_t(blockIdx.x) * kFieldTot + k] = t;
   }
-  if (threadIdx.x == 0) part[size_t(blockIdx.x) * 8 + 7] = 0.0;
 }
 
 // out[w] = sum_r part[r*width + w], fixed order
@@ -716,11 +728,17 @@ __global__ void k_cpx_real(const cpx<double>* __restrict__ c, size_t N, double* 
   const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
   if (p < N) out[p] = c[p].x;
 }
-__global__ void k_add_bext(const double* __restrict__ f, size_t N, double b0, double b1, double b2,
+__global__ void k_add_bext(const double* __restrict__ f, int ny, int nz, size_t N, double b0,
+                           double b1, double b2, double l0, double l1, double l2, double l3,
                            double* __restrict__ out) {
   const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
   if (p < N) {
-    out[p] = f[p];
+    const size_t nyz = size_t(ny) * nz;
+    const int ix = int(p / nyz);
+    const int rem = int(p - size_t(ix) * nyz);
+    const int iy = rem / nz;
+    const int iz = rem - iy * nz;
+    out[p] = f[p] + (l0 * ix + l1 * iy + l2 * iz + l3);
     out[N + p] = f[N + p] + b0;
     out[2 * N + p] = f[2 * N + p] + b1;
     out[3 * N + p] = f[3 * N + p] + b2;
@@ -1076,7 +1094,8 @@ __global__ __launch_bounds__(256) void k_obs_row(ObsInputs in, double* __restric
     const double* ft = in.field_tot;
     const double dV = in.dV;
     const double Ne = ft[0] * dV, Mx = ft[1] * dV, My = ft[2] * dV, Mz = ft[3] * dV;
-    const double Eloc = ft[4] * dV, EH = ft[5] * dV, Exc = ft[6] * dV;
+    const double Eloc = (ft[4] + in.efield[0] * ft[8] + in.efield[1] * ft[9] + in.efield[2] * ft[10]) * dV;
+    const double EH = ft[5] * dV, Exc = ft[6] * dV;
     const double EZ = in.muB_B[0] * Mx + in.muB_B[1] * My + in.muB_B[2] * Mz;
     row[0] = in.t;
     row[1] = Ne;
@@ -1308,12 +1327,14 @@ hipError_t launch_density(const void* psi, const double* occ, int S, size_t N, d
 }
 
 hipError_t launch_fields(const double* rho, const double* vext, const double* vH, int xc,
-                         double thr, size_t N, double* fields, float* fields32, double* part,
-                         int* nblk_out, hipStream_t st) {
+                         double thr, const int n[3], const double cell[3], double* fields,
+                         float* fields32, double* part, int* nblk_out, hipStream_t st) {
+  const size_t N = size_t(n[0]) * n[1] * n[2];
   const unsigned nb = nblocks(N, 256);
   *nblk_out = int(nb);
-  hipLaunchKernelGGL(k_fields, dim3(nb), dim3(256), 0, st, rho, vext, vH, xc, thr, N, fields,
-                     fields32, part);
+  hipLaunchKernelGGL(k_fields, dim3(nb), dim3(256), 0, st, rho, vext, vH, xc, thr, n[1], n[2],
+                     cell[0] / n[0], cell[1] / n[1], cell[2] / n[2], 0.5 * cell[0], 0.5 * cell[1],
+                     0.5 * cell[2], N, fields, fields32, part);
   return hipGetLastError();
 }
 
@@ -1332,10 +1353,11 @@ hipError_t launch_cpx_real(const void* c, size_t N, double* out, hipStream_t st)
                      reinterpret_cast<const cpx<double>*>(c), N, out);
   return hipGetLastError();
 }
-hipError_t launch_add_bext(const double* fields, size_t N, const double b[3], double* out,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(k_add_bext, dim3(nblocks(N, 256)), dim3(256), 0, st, fields, N, b[0], b[1],
-                     b[2], out);
+hipError_t launch_add_bext(const double* fields, const int n[3], const double b[3],
+                           const double lg[4], double* out, hipStream_t st) {
+  const size_t N = size_t(n[0]) * n[1] * n[2];
+  hipLaunchKernelGGL(k_add_bext, dim3(nblocks(N, 256)), dim3(256), 0, st, fields, n[1], n[2], N,
+                     b[0], b[1], b[2], lg[0], lg[1], lg[2], lg[3], out);
   return hipGetLastError();
 }
 hipError_t launch_to_float(const double* in, size_t n, float* out, hipStream_t st) {

@@ -38,6 +38,11 @@ class BField(ctypes.Structure):
     _fields_ = [("B0", c_double * 3), ("npulses", c_int), ("pulses", POINTER(Pulse))]
 
 
+class LaserPulse(ctypes.Structure):
+    _fields_ = [("A", c_double), ("omega", c_double), ("t0", c_double), ("tau", c_double),
+                ("phase", c_double), ("pol", c_double * 3)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("n", c_int * 3), ("cell", c_double * 3), ("nstates", c_int),
                 ("occ", POINTER(c_double)), ("natoms", c_int), ("positions", POINTER(c_double)),
@@ -71,6 +76,8 @@ def lib():
         L.nct_last_error.restype = ctypes.c_char_p
         L.nct_set_potentials.argtypes = [c_void_p, c_void_p, POINTER(BField), c_void_p]
         L.nct_set_potentials.restype = c_int
+        L.nct_set_laser.argtypes = [c_void_p, c_int, POINTER(LaserPulse)]
+        L.nct_set_laser.restype = c_int
         L.nct_density_magnetization.argtypes = [c_void_p, c_void_p, c_double, c_void_p,
                                                 POINTER(c_double), c_int]
         L.nct_density_magnetization.restype = c_int
@@ -205,6 +212,15 @@ class System:
                                              ctypes.byref(bf) if bf is not None else None,
                                              _tptr(fields)))
 
+    def set_laser(self, pulses=None):
+        """Uniform electric pulses (objects with A, omega, t0, tau, phase, pol); None or [] removes."""
+        pl = list(pulses or [])
+        arr = (LaserPulse * max(1, len(pl)))()
+        for k, q in enumerate(pl):
+            arr[k] = LaserPulse(q.A, q.omega, q.t0, q.tau, getattr(q, "phase", 0.0),
+                                (c_double * 3)(*q.pol))
+        self._check(lib().nct_set_laser(self.h, len(pl), ctypes.cast(arr, POINTER(LaserPulse)) if pl else None))
+
     def density_magnetization(self, psi, t: float = 0.0, rho_v=None, totals: bool = False,
                               update_fields: bool = False):
         tot = np.zeros(4)
@@ -262,6 +278,8 @@ def system_from_workload(w, precision: int = NCT_FP64, tape_steps: int = 0, dt=N
                precision=precision, tape_steps=tape_steps, overlap=overlap, stream=stream)
     v = torch.from_numpy(np.ascontiguousarray(w.v_ext)).to("cuda")
     s.set_potentials(v_ext=v, B0=w.bfield.B0, pulses=w.bfield.pulses)
+    if getattr(w, "laser", None):
+        s.set_laser(w.laser)
     torch.cuda.synchronize()
     return s
 

@@ -22,7 +22,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for f in ["nct_create_system", "nct_destroy_system", "nct_last_error", "nct_set_potentials",
               "nct_density_magnetization", "nct_apply_hamiltonian", "nct_step",
-              "nct_backward_step", "nct_magnetization_seed", "nct_get_fields", "nct_version"]:
+              "nct_backward_step", "nct_magnetization_seed", "nct_get_fields", "nct_version",
+              "nct_set_laser"]:
         assert f in names
 
 
@@ -46,6 +47,7 @@ int main(void) {
          offsetof(nct_params, r_sphere), offsetof(nct_params, dt), offsetof(nct_params, tape_steps),
          offsetof(nct_params, overlap), offsetof(nct_params, stream));
   printf("%zu %zu\n", offsetof(nct_pulse, e1), offsetof(nct_bfield, pulses));
+  printf("%zu %zu\n", sizeof(nct_laser_pulse), offsetof(nct_laser_pulse, pol));
   return 0;
 }
 '''
@@ -62,6 +64,7 @@ int main(void) {
     assert vals[4:11] == [P.nstates.offset, P.occ.offset, P.r_sphere.offset, P.dt.offset,
                           P.tape_steps.offset, P.overlap.offset, P.stream.offset]
     assert vals[11:13] == [nct.Pulse.e1.offset, nct.BField.pulses.offset]
+    assert vals[13:15] == [ctypes.sizeof(nct.LaserPulse), nct.LaserPulse.pol.offset]
 
 
 def test_binding_refuses_without_gpu():
