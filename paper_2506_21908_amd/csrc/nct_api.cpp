@@ -211,12 +211,19 @@ hipError_t timed_on(nct_system* s, hipStream_t st, int k, double bytes, double f
   if (!s->timing || !((s->timing_mask >> k) & 1u)) return launch();
   hipEvent_t a = take_event(s), b = take_event(s);
   if (!a || !b) return launch();
-  hipError_t e = hipEventRecord(a, st);
-  if (e != hipSuccess) return e;
-  e = launch();
-  if (e != hipSuccess) return e;
-  e = hipEventRecord(b, st);
-  if (e != hipSuccess) return e;
+  (void)st;  // the events ride on the dispatches themselves, on the stream they are launched on
+  LaunchEvents& le = launch_events();
+  le.start = a;
+  le.stop = b;
+  le.used = false;
+  const hipError_t e = launch();
+  const bool used = le.used;
+  le = LaunchEvents{};
+  if (e != hipSuccess || !used) {
+    s->free_events.push_back(a);
+    s->free_events.push_back(b);
+    return e;
+  }
   s->pending.push_back({k, a, b, bytes, flops});
   return hipSuccess;
 }
@@ -1300,8 +1307,8 @@ nct_status create_impl(const nct_params* p, nct_system** out) {
   s->gtot = (double*)p0;
   if (p->tape_steps > 0 && (r = alloc_tape(s, s->tape, p->tape_steps)) != NCT_OK) return bail(r);
   if (hipStreamCreateWithFlags(&s->st2, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&s->ev_rows, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&s->ev_proj, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&s->ev_rows, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess ||
+      hipEventCreateWithFlags(&s->ev_proj, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess) {
     fail(s, NCT_ERR_HIP, "stream/event creation failed");
     return bail(NCT_ERR_HIP);
   }
@@ -1310,10 +1317,10 @@ nct_status create_impl(const nct_params* p, nct_system** out) {
     s->S0 = (s->S + 1) / 2;
     if (hipStreamCreateWithFlags(&s->stB, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&s->stB2, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&s->evB_rows, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&s->evB_proj, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&s->evB_rows, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&s->evB_proj, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_join, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess) {
       fail(s, NCT_ERR_HIP, "stream/event creation failed");
       return bail(NCT_ERR_HIP);
     }

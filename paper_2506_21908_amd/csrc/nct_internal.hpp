@@ -140,6 +140,16 @@ hipError_t launch_density_backprop(const void* psi, const double* occ, const dou
                                    size_t N, int add, void* lam, hipStream_t st);
 hipError_t launch_real_to_cpx(const double* r, size_t N, void* out, hipStream_t st);
 
+// HIP events attached to the next kernel dispatches of this host thread (set by the library's
+// timing wrapper around one launcher call): 'start' goes with the first dispatch and 'stop' with
+// every dispatch, so the pair spans all kernels of the launcher without extra stream packets.
+struct LaunchEvents {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+  bool used = false;
+};
+LaunchEvents& launch_events();
+
 bool plane_pair_supported(int ny, int nz);
 bool line_supported(int n);
 

@@ -13,6 +13,7 @@
 // contraction <beta|psi> and its scatter-back run on the matrix cores
 // (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32).
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 #include <cstdint>
@@ -1150,6 +1151,24 @@ __global__ void k_axpby(cpx<R>* __restrict__ y, const cpx<R>* __restrict__ x, si
 // ================================================================ launchers
 static inline unsigned nblocks(size_t n, unsigned bs) { return unsigned((n + bs - 1) / bs); }
 
+LaunchEvents& launch_events() {
+  static thread_local LaunchEvents ev;
+  return ev;
+}
+
+// Every dispatch goes through here: with timing events pending they ride on the dispatch itself.
+template <typename F, typename... Args>
+static void nct_launch(F kern, dim3 grid, dim3 block, size_t lds, hipStream_t st, Args... args) {
+  LaunchEvents& ev = launch_events();
+  if (ev.stop) {
+    hipExtLaunchKernelGGL(kern, grid, block, std::uint32_t(lds), st, ev.used ? nullptr : ev.start,
+                          ev.stop, 0u, args...);
+    ev.used = true;
+  } else {
+    hipLaunchKernelGGL(kern, grid, block, lds, st, args...);
+  }
+}
+
 #define NCT_PLANE_PAIRS(X) \
   X(8, 8) X(12, 12) X(16, 16) X(24, 24) X(32, 32) X(48, 48) X(64, 64) X(96, 96) \
   X(8, 16) X(16, 8) X(12, 16) X(16, 12) X(16, 24) X(24, 16)
@@ -1186,13 +1205,13 @@ static hipError_t launch_plane_stage_m(int S, int NX, const StageArgs<R>& a, con
     auto kern2 = k_plane_stage2<R, A, B, M>;
     hipError_t e2 = set_lds(kern2, lds2);
     if (e2 != hipSuccess) return e2;
-    hipLaunchKernelGGL(kern2, dim3(grid), dim3(2 * plane2_nth<R>(A * B)), lds2, st, a, pt, ty, tz, S, NX);
+    nct_launch(kern2, dim3(grid), dim3(2 * plane2_nth<R>(A * B)), lds2, st, a, pt, ty, tz, S, NX);
   } else {
     constexpr size_t lds = plane_lds_bytes<A, B>(sizeof(cpx<R>));
     auto kern = k_plane_stage<R, A, B, M>;
     hipError_t e = set_lds(kern, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(plane_nt(A * B)), lds, st, a, pt, ty, tz, S, NX);
+    nct_launch(kern, dim3(grid), dim3(plane_nt(A * B)), lds, st, a, pt, ty, tz, S, NX);
   }
   return hipGetLastError();
 }
@@ -1223,7 +1242,7 @@ hipError_t launch_plane_fwd(const int n[3], int B, const void* in, void* out, vo
     auto kern = k_plane_fwd<R, A, BB>;                                                      \
     hipError_t e = set_lds(kern, lds);                                                      \
     if (e != hipSuccess) return e;                                                          \
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(plane_nt(A * BB)), lds, st,                   \
+    nct_launch(kern, dim3(grid), dim3(plane_nt(A * BB)), lds, st,                   \
                        reinterpret_cast<const cpx<R>*>(in), reinterpret_cast<cpx<R>*>(out),  \
                        reinterpret_cast<cpx<R>*>(W), p,                                     \
                        reinterpret_cast<const cpx<R>*>(twy), reinterpret_cast<const cpx<R>*>(twz), \
@@ -1245,7 +1264,7 @@ hipError_t launch_plane_inv(const int n[3], int B, const void* in, void* out, R 
     auto kern = k_plane_inv<R, A, BB>;                                                      \
     hipError_t e = set_lds(kern, lds);                                                      \
     if (e != hipSuccess) return e;                                                          \
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(plane_nt(A * BB)), lds, st,                   \
+    nct_launch(kern, dim3(grid), dim3(plane_nt(A * BB)), lds, st,                   \
                        reinterpret_cast<const cpx<R>*>(in), reinterpret_cast<cpx<R>*>(out),  \
                        scale, reinterpret_cast<const cpx<R>*>(twy),                         \
                        reinterpret_cast<const cpx<R>*>(twz), B, n[0]);                      \
@@ -1267,11 +1286,11 @@ static hipError_t launch_xpass_tc(int B, int NYZ, const void* src, void* dst, co
   // costs occupancy
   const dim3 grid(unsigned(B) * unsigned(tiles));
   if (cache_mode >= 2)
-    hipLaunchKernelGGL((k_xpass<R, NX, TC, 1, 2>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_);
+    nct_launch((k_xpass<R, NX, TC, 1, 2>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_);
   else if (cache_mode == 1)
-    hipLaunchKernelGGL((k_xpass<R, NX, TC, 1, 1>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_);
+    nct_launch((k_xpass<R, NX, TC, 1, 1>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_);
   else
-    hipLaunchKernelGGL((k_xpass<R, NX, TC, 1, 0>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_);
+    nct_launch((k_xpass<R, NX, TC, 1, 0>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_);
   return hipGetLastError();
 }
 
@@ -1302,12 +1321,12 @@ hipError_t launch_xpass_energy(const int n[3], int B, const void* src, const R* 
     constexpr int TCP = xpass_tc<R>(A);                                                     \
     if (NYZ % TCP == 0) {                                                                   \
       *ntiles_out = NYZ / TCP;                                                              \
-      hipLaunchKernelGGL((k_xpass_energy<R, A, TCP>), dim3(unsigned(B) * unsigned(NYZ / TCP)), \
+      nct_launch((k_xpass_energy<R, A, TCP>), dim3(unsigned(B) * unsigned(NYZ / TCP)), \
                          dim3(XP_NT), 0, st, reinterpret_cast<const cpx<R>*>(src), NYZ, g2x,  \
                          g2yz, kscale, reinterpret_cast<const cpx<R>*>(twx), part);          \
     } else {                                                                                \
       *ntiles_out = NYZ / 16;                                                               \
-      hipLaunchKernelGGL((k_xpass_energy<R, A, 16>), dim3(unsigned(B) * unsigned(NYZ / 16)),  \
+      nct_launch((k_xpass_energy<R, A, 16>), dim3(unsigned(B) * unsigned(NYZ / 16)),  \
                          dim3(XP_NT), 0, st, reinterpret_cast<const cpx<R>*>(src), NYZ, g2x,  \
                          g2yz, kscale, reinterpret_cast<const cpx<R>*>(twx), part);          \
     }                                                                                       \
@@ -1321,7 +1340,7 @@ hipError_t launch_xpass_energy(const int n[3], int B, const void* src, const R* 
 template <typename R>
 hipError_t launch_density(const void* psi, const double* occ, int S, size_t N, double* rho,
                           hipStream_t st) {
-  hipLaunchKernelGGL((k_density<R>), dim3(nblocks(N, 256)), dim3(256), 0, st,
+  nct_launch((k_density<R>), dim3(nblocks(N, 256)), dim3(256), 0, st,
                      reinterpret_cast<const cpx<R>*>(psi), occ, S, N, rho);
   return hipGetLastError();
 }
@@ -1332,7 +1351,7 @@ hipError_t launch_fields(const double* rho, const double* vext, const double* vH
   const size_t N = size_t(n[0]) * n[1] * n[2];
   const unsigned nb = nblocks(N, 256);
   *nblk_out = int(nb);
-  hipLaunchKernelGGL(k_fields, dim3(nb), dim3(256), 0, st, rho, vext, vH, xc, thr, n[1], n[2],
+  nct_launch(k_fields, dim3(nb), dim3(256), 0, st, rho, vext, vH, xc, thr, n[1], n[2],
                      cell[0] / n[0], cell[1] / n[1], cell[2] / n[2], 0.5 * cell[0], 0.5 * cell[1],
                      0.5 * cell[2], N, fields, fields32, part);
   return hipGetLastError();
@@ -1340,28 +1359,28 @@ hipError_t launch_fields(const double* rho, const double* vext, const double* vH
 
 hipError_t launch_reduce_rows(const double* part, int nrows, int width, double* out,
                               hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(256), 0, st, part, nrows, width, out);
+  nct_launch(k_reduce_rows, dim3(1), dim3(256), 0, st, part, nrows, width, out);
   return hipGetLastError();
 }
 hipError_t launch_rho_to_n(const double* rho, size_t N, void* ncpx, hipStream_t st) {
-  hipLaunchKernelGGL(k_rho_to_n, dim3(nblocks(N, 256)), dim3(256), 0, st, rho, N,
+  nct_launch(k_rho_to_n, dim3(nblocks(N, 256)), dim3(256), 0, st, rho, N,
                      reinterpret_cast<cpx<double>*>(ncpx));
   return hipGetLastError();
 }
 hipError_t launch_cpx_real(const void* c, size_t N, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_cpx_real, dim3(nblocks(N, 256)), dim3(256), 0, st,
+  nct_launch(k_cpx_real, dim3(nblocks(N, 256)), dim3(256), 0, st,
                      reinterpret_cast<const cpx<double>*>(c), N, out);
   return hipGetLastError();
 }
 hipError_t launch_add_bext(const double* fields, const int n[3], const double b[3],
                            const double lg[4], double* out, hipStream_t st) {
   const size_t N = size_t(n[0]) * n[1] * n[2];
-  hipLaunchKernelGGL(k_add_bext, dim3(nblocks(N, 256)), dim3(256), 0, st, fields, n[1], n[2], N,
+  nct_launch(k_add_bext, dim3(nblocks(N, 256)), dim3(256), 0, st, fields, n[1], n[2], N,
                      b[0], b[1], b[2], lg[0], lg[1], lg[2], lg[3], out);
   return hipGetLastError();
 }
 hipError_t launch_to_float(const double* in, size_t n, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_to_float, dim3(nblocks(n, 256)), dim3(256), 0, st, in, n, out);
+  nct_launch(k_to_float, dim3(nblocks(n, 256)), dim3(256), 0, st, in, n, out);
   return hipGetLastError();
 }
 
@@ -1372,15 +1391,15 @@ hipError_t launch_proj_contract(const ProjTables& pt, const void* W, int S, doub
   const unsigned ntile = unsigned((S + 15) / 16);
   const dim3 grid(pt.natoms, ntile, pt.max_kchunks);
   if (pt.PP == 16)
-    hipLaunchKernelGGL((k_proj_contract<R, 16>), grid, dim3(64), 0, st, pt,
+    nct_launch((k_proj_contract<R, 16>), grid, dim3(64), 0, st, pt,
                        reinterpret_cast<const cpx<R>*>(W), S, reinterpret_cast<cpx<double>*>(Cpart));
   else
-    hipLaunchKernelGGL((k_proj_contract<R, 32>), grid, dim3(64), 0, st, pt,
+    nct_launch((k_proj_contract<R, 32>), grid, dim3(64), 0, st, pt,
                        reinterpret_cast<const cpx<R>*>(W), S, reinterpret_cast<cpx<double>*>(Cpart));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t total = size_t(pt.natoms) * pt.PP * S;
-  hipLaunchKernelGGL((k_proj_reduce<R>), dim3(nblocks(total, 256)), dim3(256), 0, st, pt,
+  nct_launch((k_proj_reduce<R>), dim3(nblocks(total, 256)), dim3(256), 0, st, pt,
                      reinterpret_cast<const cpx<double>*>(Cpart), S, dV,
                      reinterpret_cast<cpx<double>*>(C), reinterpret_cast<cpx<R>*>(EC));
   return hipGetLastError();
@@ -1393,23 +1412,23 @@ hipError_t launch_proj_scatter(const ProjTables& pt, const void* EC, int S, void
   const unsigned ntile = unsigned((S + 15) / 16);
   const dim3 grid(pt.natoms, pt.max_rowtiles, ntile);
   if (pt.PP == 16)
-    hipLaunchKernelGGL((k_proj_scatter<R, 16>), grid, dim3(64), 0, st, pt,
+    nct_launch((k_proj_scatter<R, 16>), grid, dim3(64), 0, st, pt,
                        reinterpret_cast<const cpx<R>*>(EC), S, reinterpret_cast<cpx<R>*>(Y));
   else
-    hipLaunchKernelGGL((k_proj_scatter<R, 32>), grid, dim3(64), 0, st, pt,
+    nct_launch((k_proj_scatter<R, 32>), grid, dim3(64), 0, st, pt,
                        reinterpret_cast<const cpx<R>*>(EC), S, reinterpret_cast<cpx<R>*>(Y));
   return hipGetLastError();
 }
 
 hipError_t launch_obs_row(const ObsInputs& in, double* row, hipStream_t st) {
-  hipLaunchKernelGGL(k_obs_row, dim3(1), dim3(256), 0, st, in, row);
+  nct_launch(k_obs_row, dim3(1), dim3(256), 0, st, in, row);
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_seed(const void* psi, const double* occ, int S, size_t N, double w0, double w1,
                        double w2, double scale, void* lam, hipStream_t st) {
-  hipLaunchKernelGGL((k_seed<R>), dim3(nblocks(size_t(S) * N, 256)), dim3(256), 0, st,
+  nct_launch((k_seed<R>), dim3(nblocks(size_t(S) * N, 256)), dim3(256), 0, st,
                      reinterpret_cast<const cpx<R>*>(psi), occ, S, N, w0, w1, w2, scale,
                      reinterpret_cast<cpx<R>*>(lam));
   return hipGetLastError();
@@ -1417,7 +1436,7 @@ hipError_t launch_seed(const void* psi, const double* occ, int S, size_t N, doub
 template <typename R>
 hipError_t launch_axpby(void* y, const void* x, size_t count, R a_re, R a_im, R b,
                         hipStream_t st) {
-  hipLaunchKernelGGL((k_axpby<R>), dim3(nblocks(count, 256)), dim3(256), 0, st,
+  nct_launch((k_axpby<R>), dim3(nblocks(count, 256)), dim3(256), 0, st,
                      reinterpret_cast<cpx<R>*>(y), reinterpret_cast<const cpx<R>*>(x), count, a_re,
                      a_im, b);
   return hipGetLastError();
@@ -1426,7 +1445,7 @@ hipError_t launch_axpby(void* y, const void* x, size_t count, R a_re, R a_im, R 
 template <typename R>
 hipError_t launch_pair(const void* mu, const void* w, int S, size_t N, double gamma, double* g,
                        hipStream_t st) {
-  hipLaunchKernelGGL((k_pair<R>), dim3(nblocks(N, 256)), dim3(256), 0, st,
+  nct_launch((k_pair<R>), dim3(nblocks(N, 256)), dim3(256), 0, st,
                      reinterpret_cast<const cpx<R>*>(mu), reinterpret_cast<const cpx<R>*>(w), S, N,
                      gamma, g);
   return hipGetLastError();
@@ -1436,19 +1455,19 @@ hipError_t launch_field_adjoint(const double* rho, const double* g, const double
                                 hipStream_t st) {
   const unsigned nb = nblocks(N, 256);
   *nblk_out = int(nb);
-  hipLaunchKernelGGL(k_field_adjoint, dim3(nb), dim3(256), 0, st, rho, g, pg, xc, thr, N, gnm, part);
+  nct_launch(k_field_adjoint, dim3(nb), dim3(256), 0, st, rho, g, pg, xc, thr, N, gnm, part);
   return hipGetLastError();
 }
 template <typename R>
 hipError_t launch_density_backprop(const void* psi, const double* occ, const double* gnm, int S,
                                    size_t N, int add, void* lam, hipStream_t st) {
-  hipLaunchKernelGGL((k_density_backprop<R>), dim3(nblocks(size_t(S) * N, 256)), dim3(256), 0, st,
+  nct_launch((k_density_backprop<R>), dim3(nblocks(size_t(S) * N, 256)), dim3(256), 0, st,
                      reinterpret_cast<const cpx<R>*>(psi), occ, gnm, S, N, add,
                      reinterpret_cast<cpx<R>*>(lam));
   return hipGetLastError();
 }
 hipError_t launch_real_to_cpx(const double* r, size_t N, void* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_real_to_cpx, dim3(nblocks(N, 256)), dim3(256), 0, st, r, N,
+  nct_launch(k_real_to_cpx, dim3(nblocks(N, 256)), dim3(256), 0, st, r, N,
                      reinterpret_cast<cpx<double>*>(out));
   return hipGetLastError();
 }
