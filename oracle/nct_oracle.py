@@ -24,7 +24,8 @@ parametrisation; the readings taken here are listed in the design doc and below:
     exponential of order K (default 4), predictor built from a second
     half-step of the same exponential;
   * exchange-correlation: Slater exchange (spin-scaled), locally collinear;
-    b_xc = 0 where |m| < threshold;
+    b_xc = 0 where |m| < threshold; with xc = 2 also the Perdew-Wang 1992
+    (PW92) LSDA correlation in the same locally collinear form;
   * Hartree: FFT Poisson solve with the G = 0 term dropped;
   * projectors: radial form r^l exp(-r^2/2rc^2) cut at r_sphere, normalised by
     the continuum radial integral; channel energies absorb the KB denominator;
@@ -140,6 +141,75 @@ def slater_exchange(n: np.ndarray, m: np.ndarray, thr: float = 1e-12):
     safe_mu = np.where(big, mu, 1.0)
     bxc = np.where(big, bmag / safe_mu, 0.0) * m
     return vbar, bxc, e_x
+
+
+# ----------------------------------------------------------------------------
+# correlation: PW92 LSDA correlation (J. P. Perdew and Y. Wang, Phys. Rev. B 45,
+# 13244 (1992)), applied in the locally collinear form of Eqs. LC+ALDA2 / LC+ALDA
+# ----------------------------------------------------------------------------
+# (A, alpha1, beta1, beta2, beta3, beta4) of G(rs) with p = 1, PW92 Table I
+PW92_PARA = (0.031091, 0.21370, 7.5957, 3.5876, 1.6382, 0.49294)    # eps_c(rs, zeta = 0)
+PW92_FERRO = (0.015545, 0.20548, 14.1189, 6.1977, 3.3662, 0.62517)  # eps_c(rs, zeta = 1)
+PW92_ALPHA = (0.016887, 0.11125, 10.357, 3.6231, 0.88026, 0.49671)  # -alpha_c(rs)
+PW92_FPP0 = 1.709921                                                # f''(0)
+PW92_NMIN = 1e-30
+
+
+def pw92_G(rs, par):
+    """G = -2A(1 + a1 rs) ln[1 + 1/(2A(b1 rs^1/2 + b2 rs + b3 rs^3/2 + b4 rs^2))] and dG/drs."""
+    A, a1, b1, b2, b3, b4 = par
+    srs = np.sqrt(rs)
+    q0 = -2.0 * A * (1.0 + a1 * rs)
+    q1 = 2.0 * A * (b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs)
+    q1p = A * (b1 / srs + 2.0 * b2 + 3.0 * b3 * srs + 4.0 * b4 * rs)
+    lg = np.log1p(1.0 / q1)
+    return q0 * lg, -2.0 * A * a1 * lg - q0 * q1p / (q1 * q1 + q1)
+
+
+def pw92_f(zeta):
+    """Spin interpolation f(zeta) = [(1+z)^(4/3) + (1-z)^(4/3) - 2] / (2^(4/3) - 2) and f'."""
+    d = 2.0 ** (4.0 / 3.0) - 2.0
+    up, dn = 1.0 + zeta, 1.0 - zeta
+    f = (up ** (4.0 / 3.0) + dn ** (4.0 / 3.0) - 2.0) / d
+    fp = (4.0 / 3.0) * (np.cbrt(up) - np.cbrt(dn)) / d
+    return f, fp
+
+
+def pw92_eps(rs, zeta):
+    """eps_c(rs, zeta) of PW92 Eq. (8) with its derivatives (eps, d eps/d rs, d eps/d zeta)."""
+    e0, d0 = pw92_G(rs, PW92_PARA)
+    e1, d1 = pw92_G(rs, PW92_FERRO)
+    ma, dma = pw92_G(rs, PW92_ALPHA)
+    ac, dac = -ma, -dma
+    f, fp = pw92_f(zeta)
+    z4 = zeta ** 4
+    eps = e0 + ac * f * (1.0 - z4) / PW92_FPP0 + (e1 - e0) * f * z4
+    deps_rs = d0 * (1.0 - f * z4) + d1 * f * z4 + dac * f * (1.0 - z4) / PW92_FPP0
+    deps_z = (4.0 * zeta ** 3 * f * (e1 - e0 - ac / PW92_FPP0)
+              + fp * (z4 * (e1 - e0) + (1.0 - z4) * ac / PW92_FPP0))
+    return eps, deps_rs, deps_z
+
+
+def pw92_correlation(n: np.ndarray, m: np.ndarray, thr: float = 1e-12):
+    """Returns (vbar_c, b_c[3], e_c) with e_c = n eps_c the correlation energy per volume.
+
+    zeta = |m|/n (clamped to [0, 1]), rs = (3/(4 pi n))^(1/3);
+    v_up/dn = eps - (rs/3) d eps/d rs - (zeta -/+ 1) d eps/d zeta;
+    vbar_c = (v_up + v_dn)/2,  b_c = (v_up - v_dn)/2 m/|m| = (d eps/d zeta) m/|m|  (zero where
+    |m| < thr);  nothing where n <= 1e-30.
+    """
+    mu = np.sqrt(m[0] ** 2 + m[1] ** 2 + m[2] ** 2)
+    ok = n > PW92_NMIN
+    ns = np.where(ok, n, 1.0)
+    rs = np.cbrt(3.0 / (4.0 * math.pi * ns))
+    zeta = np.clip(mu / ns, 0.0, 1.0)
+    eps, drs, dz = pw92_eps(rs, zeta)
+    vbar = np.where(ok, eps - rs / 3.0 * drs - zeta * dz, 0.0)
+    big = ok & (mu >= thr)
+    safe_mu = np.where(big, mu, 1.0)
+    bc = np.where(big, dz / safe_mu, 0.0) * m
+    ec = np.where(ok, n * eps, 0.0)
+    return vbar, bc, ec
 
 
 def slater_exchange_jvp(n, m, dn, dm, thr: float = 1e-12):
@@ -435,6 +505,9 @@ def fields_from_density(sysd: System, rho_v: np.ndarray, t: float) -> Fields:
     vH = hartree(n, grid) if sysd.hartree else np.zeros_like(n)
     if sysd.xc:
         vbar, bxc, ex = slater_exchange(n, m, sysd.thr)
+        if sysd.xc >= 2:
+            vc, bc, ec = pw92_correlation(n, m, sysd.thr)
+            vbar, bxc, ex = vbar + vc, bxc + bc, ex + ec
     else:
         vbar, bxc, ex = np.zeros_like(n), np.zeros_like(m), np.zeros_like(n)
     B = sysd.bfield.B(t)
@@ -547,6 +620,8 @@ def _density_jvp(psi, dpsi, occ):
 
 
 def _fields_jvp(sysd: System, rho_v, drho_v, dB):
+    if sysd.xc >= 2:
+        raise NotImplementedError("tangent-linear fields cover exchange only (xc <= 1)")
     n, m = charge_and_magnetization(rho_v)
     dn, dm = charge_and_magnetization(drho_v)
     dvH = hartree(dn, sysd.grid) if sysd.hartree else np.zeros_like(n)

@@ -194,6 +194,62 @@ def test_slater_jvp_matches_central_differences():
 
 
 # ---------------------------------------------------------------- Hartree
+# ---------------------------------------------------------------- PW92 correlation (xc = 2)
+def test_pw92_high_density_limit():
+    """eps_c -> c0 ln rs - c1 as rs -> 0 with the exact Gell-Mann-Brueckner coefficient
+    c0 = (1 - ln 2)/pi^2 (half of it when fully polarised) and PW92's c1 = 0.046644."""
+    c0 = (1.0 - math.log(2.0)) / math.pi ** 2
+    for z, c in ((0.0, c0), (1.0, 0.5 * c0)):
+        rs = 1e-8
+        e1 = float(O.pw92_eps(np.array(rs), np.array(z))[0])
+        e2 = float(O.pw92_eps(np.array(rs * 1.01), np.array(z))[0])
+        # PW92 prints A to 5 significant digits (0.031091, 0.015545)
+        assert abs((e2 - e1) / math.log(1.01) / c - 1.0) < 5e-5
+    e = float(O.pw92_eps(np.array(1e-6), np.array(0.0))[0])
+    assert abs(-(e - c0 * math.log(1e-6)) - 0.046644) < 5e-6
+
+
+def test_pw92_uniform_gas_textbook_values():
+    """Unpolarised correlation energies of the uniform electron gas (Ceperley-Alder, as fitted by
+    PW92): -0.0448, -0.0282, -0.0186 Ha at rs = 2, 5, 10."""
+    for rs, ref in ((2.0, -0.0448), (5.0, -0.0282), (10.0, -0.0186)):
+        assert abs(float(O.pw92_eps(np.array(rs), np.array(0.0))[0]) - ref) < 2e-4
+
+
+def test_pw92_spin_interpolation():
+    f = lambda z: float(O.pw92_f(np.array(z))[0])
+    fp = lambda z: float(O.pw92_f(np.array(z))[1])
+    assert f(0.0) == 0.0 and abs(f(1.0) - 1.0) < 1e-15 and abs(f(-1.0) - 1.0) < 1e-15
+    h = 1e-4
+    assert abs((f(h) - 2 * f(0.0) + f(-h)) / h ** 2 - O.PW92_FPP0) < 1e-6
+    for z in (0.2, 0.7, 0.95):
+        assert abs((f(z + 1e-6) - f(z - 1e-6)) / 2e-6 - fp(z)) < 1e-8
+
+
+def test_pw92_potentials_are_energy_derivatives():
+    """v_up/dn = d(n eps_c)/d n_up/dn (central differences), through the locally collinear map
+    (n, m) -> (vbar_c, b_c) with eigenvalues v_up, v_dn of the 2x2 V_c along +/- mhat."""
+    def e_of(nu, nd):
+        n = nu + nd
+        rs = (3.0 / (4.0 * math.pi * n)) ** (1.0 / 3.0)
+        return n * float(O.pw92_eps(np.array(rs), np.array((nu - nd) / n))[0])
+    mhat = np.array([0.3, -0.4, math.sqrt(1 - 0.25)])
+    for n, z in ((0.5, 0.0), (0.05, 0.3), (0.002, 0.8), (1.3, 0.97)):
+        nu, nd = 0.5 * n * (1 + z), 0.5 * n * (1 - z)
+        h = 1e-6 * n
+        vu = (e_of(nu + h, nd) - e_of(nu - h, nd)) / (2 * h)
+        vd = (e_of(nu, nd + h) - e_of(nu, nd - h)) / (2 * h)
+        m = (z * n * mhat)[:, None, None, None]
+        vbar, bc, ec = O.pw92_correlation(np.full((1, 1, 1), n), m)
+        b = bc[:, 0, 0, 0]
+        if z > 0:
+            assert np.linalg.norm(np.cross(b, mhat)) < 1e-15      # no local torque
+        bm = float(np.dot(b, mhat))
+        assert abs(float(vbar.ravel()[0]) + bm - vu) < 1e-7
+        assert abs(float(vbar.ravel()[0]) - bm - vd) < 1e-7
+        assert abs(float(ec.ravel()[0]) - e_of(nu, nd)) < 1e-15
+
+
 def test_hartree_cosine_closed_form():
     """n = cos(G.r) gives v_H = (4 pi/|G|^2) cos(G.r); a constant density gives v_H = 0."""
     grid = O.Grid((8, 6, 12), (4.0, 3.0, 6.0))
@@ -530,6 +586,19 @@ def test_energy_conservation_second_order():
         _, obs = O.run(sysd, w.psi0, int(round(0.4 / dt)))
         drifts.append(abs(obs[-1, 5] - obs[0, 5]))
     assert drifts[1] < drifts[0]
+    assert 2.5 < drifts[0] / drifts[1] < 6.0
+
+
+def test_energy_conservation_second_order_with_correlation():
+    """xc = 2 (exchange + PW92): the energy still drifts only at second order in dt, which holds
+    only if the correlation potentials are the functional derivative of int n eps_c."""
+    drifts = []
+    for dt in (0.04, 0.02):
+        w = I.make_system(n=(8, 8, 8), L=(7.0,) * 3, nstates=3, natoms=1, case=9, dt=dt, xc=2,
+                          bfield=I.BField(B0=(0.0, 0.0, 0.05)))
+        sysd = O.system_from_workload(w)
+        _, obs = O.run(sysd, w.psi0, int(round(0.4 / dt)))
+        drifts.append(abs(obs[-1, 5] - obs[0, 5]))
     assert 2.5 < drifts[0] / drifts[1] < 6.0
 
 
