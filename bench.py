@@ -21,6 +21,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "TDDFT steps/s + Hψ HBM GB/s, FP64 vs FP32-mixed; adjoint/forward time ratio"
 HBM_PEAK_GBS = 8000.0
+XC_NAMES = {0: "none", 1: "Slater exchange, locally collinear",
+            2: "Slater exchange + PW92 correlation (LSDA), locally collinear"}
 WORKLOADS = {"tiny": 0, "cluster": 1, "solid": 2, "grad": 3, "large": 4, "laser": 5}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2506_21908_amd", "csrc", "nct_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "plane_stage_cluster48_fp64_traffic.md")
@@ -92,6 +94,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="cluster", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--xc", type=int, default=None, choices=[0, 1, 2],
+                    help="override the workload's exchange-correlation (2: + PW92 correlation)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-mixed comparison run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
@@ -112,6 +116,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     w = I.workload(WORKLOADS[args.workload])
+    if args.xc is not None:
+        w.xc = args.xc
     print(f"[bench] workload {w.name} built", file=sys.stderr, flush=True)
 
     if args.copy_probe:
@@ -184,7 +190,7 @@ def main():
                    "spinor_states": w.nstates, "atoms": w.natoms,
                    "projectors_per_atom": sum(c.twoj + 1 for c in w.channels),
                    "dt": w.dt, "taylor_order": w.taylor_order, "propagator": "ETRS",
-                   "xc": "Slater exchange, locally collinear", "hartree": "FFT",
+                   "xc": XC_NAMES[w.xc], "hartree": "FFT",
                    "laser": [dataclass_dict(p) for p in w.laser] or None,
                    "precision": args.precision, "parallelism": "single GPU"},
         "roofline": {"kernel": "k_plane_stage (fused plane pass)", "bound": "hbm",
@@ -206,7 +212,7 @@ def main():
         out["fp32_mixed"] = {"value": args.steps / el2, "unit": "steps/s",
                              "ms_per_step": 1e3 * el2 / args.steps,
                              "plane_stage_GBps": (by2 / (ms2 * 1e-3) / 1e9) if ms2 > 0 else None}
-    if not args.no_adjoint:
+    if not args.no_adjoint and w.xc <= 1:
         C = args.adjoint_segment
         s = nct.system_from_workload(w, precision=pflag, tape_steps=C)
         psi = nct.states_to_device(w.psi0, pflag)

@@ -15,7 +15,8 @@
  *     Im rho_ud}, Eq. (density4); m_x = 2 Re rho_ud, m_y = -2 Im rho_ud,
  *     m_z = rho_uu - rho_dd, Eqs. (rho1-3).
  *   - Exchange-correlation: adiabatic, locally collinear, Eqs. (LC+ALDA2),
- *     (LC+ALDA); Slater exchange; b_xc = 0 where |m| < m_threshold.
+ *     (LC+ALDA); Slater exchange, optionally with the Perdew-Wang 1992 LSDA
+ *     correlation (Phys. Rev. B 45, 13244); b_xc = 0 where |m| < m_threshold.
  *   - Hartree: Eq. (KSpot) solved by FFT, G = 0 term dropped.
  *   - Optional uniform electric (laser) pulse E(t) with the temporal profile of
  *     the optical runs of Sec. 4.7, in the length gauge (see nct_set_laser).
@@ -110,7 +111,8 @@ typedef struct {
   int nchannels;              /* projector channels per atom (0: no nonlocal term) */
   const nct_channel *channels;/* host [nchannels], the same table for every atom */
   double r_sphere;            /* projector sphere radius (bohr), < half the smallest cell edge */
-  int xc;                     /* 0: none; 1: Slater exchange, locally collinear */
+  int xc;                     /* 0: none; 1: Slater exchange; 2: Slater exchange + PW92 correlation
+                                 (LSDA); both locally collinear.  nct_backward_step needs xc <= 1 */
   int hartree;                /* 0: none; 1: FFT Poisson */
   double m_threshold;         /* |m| below which b_xc = 0 (bohr^-3) */
   double dt;                  /* time step (a.u.) */
@@ -184,8 +186,8 @@ nct_status nct_apply_hamiltonian(nct_system *sys, const void *psi_dev, void *hps
  * computed from psi itself.  obs_host, if non-NULL, receives [nsteps][13] doubles after each
  * step: t, N_e, M_x, M_y, M_z, E_total, E_kin, E_loc, E_NL, E_H, E_xc, E_Z,
  * max_i |<psi_i|psi_i> - 1|, with
- *   E = sum_i f_i <psi_i|T|psi_i> + int v_ext n + sum_i f_i sum_p E_p |C_p,i|^2
- *       + 1/2 int v_H n + int e_xc + mu_B B.M.
+ *   E = sum_i f_i <psi_i|T|psi_i> + int (v_ext + v_E(t)) n + sum_i f_i sum_p E_p |C_p,i|^2
+ *       + 1/2 int v_H n + int e_xc + mu_B B.M  (e_xc: exchange, plus PW92 correlation if xc = 2).
  * tape nonzero: record what nct_backward_step needs for each of these steps (requires
  * nsteps <= params.tape_steps); the record of step k of this call has tape_index k.
  * Returns NCT_ERR_NONFINITE if N_e became non-finite. */
@@ -205,7 +207,9 @@ nct_status nct_magnetization_seed(nct_system *sys, const void *psi_dev, const do
  *   dLdB_host      host double[6]: dL/dB_ext(t_n) (3) and dL/dB_ext(t_n + dt) (3);
  *   dLdtheta_host  host double[2*npulses]: dL/d(A_k) then dL/d(omega_k) are ADDED to it
  *                  (accumulate over steps), or NULL.
- * lam_np1_dev and lam_n_dev may be the same buffer. */
+ * lam_np1_dev and lam_n_dev may be the same buffer.  With self-consistent fields the adjoint
+ * covers xc <= 1 (NCT_ERR_UNSUPPORTED for xc = 2).  A laser (nct_set_laser) is re-applied in
+ * the reverse stages at the forward times. */
 nct_status nct_backward_step(nct_system *sys, int tape_index, const void *psi_n_dev, double t_n,
                              const void *lam_np1_dev, void *lam_n_dev, double *dLdB_host,
                              double *dLdtheta_host);

@@ -1215,6 +1215,7 @@ nct_status create_impl(const nct_params* p, nct_system** out) {
     return fail(nullptr, NCT_ERR_UNSUPPORTED, "plane (%d, %d) not built", p->n[1], p->n[2]);
   if (p->nstates < 1) return fail(nullptr, NCT_ERR_ARG, "nstates must be >= 1");
   if (p->taylor_order < 1 || p->taylor_order > 16) return fail(nullptr, NCT_ERR_ARG, "taylor_order in 1..16");
+  if (p->xc < 0 || p->xc > 2) return fail(nullptr, NCT_ERR_ARG, "xc must be 0, 1 or 2");
   if (p->precision != NCT_FP64 && p->precision != NCT_FP32_MIXED)
     return fail(nullptr, NCT_ERR_ARG, "precision must be NCT_FP64 or NCT_FP32_MIXED");
   if (!(p->dt > 0)) return fail(nullptr, NCT_ERR_ARG, "dt must be > 0");
@@ -1484,6 +1485,8 @@ nct_status nct_backward_step(nct_system* s, int tape_index, const void* psi_n, d
   if (!s) return NCT_ERR_ARG;
   if (!lam_np1 || !lam_n) return fail(s, NCT_ERR_ARG, "lam_np1 / lam_n is NULL");
   if (s->frozen && !s->fields_valid) return fail(s, NCT_ERR_STATE, "no fields");
+  if (s->prm.xc >= 2 && !s->frozen)
+    return fail(s, NCT_ERR_UNSUPPORTED, "the adjoint step covers exchange only (xc <= 1)");
   nct_system::Tape* T = nullptr;
   int idx = 0;
   nct_status r;

@@ -643,6 +643,44 @@ __global__ __launch_bounds__(256) void k_density(const cpx<R>* __restrict__ psi,
 //   n_s = (n +/- |m|)/2, v_s = -(6/pi)^(1/3) n_s^(1/3), vbar = (v_up+v_dn)/2,
 //   b_xc = (v_up - v_dn)/2 m/|m| (0 below threshold), e_x = -(3/4)(6/pi)^(1/3) sum n_s^(4/3).
 // v_up - v_dn is evaluated as -(6/pi)^(1/3) (n_up - n_dn) / (n_up^(2/3) + (n_up n_dn)^(1/3) + n_dn^(2/3)).
+// PW92 LSDA correlation (J. P. Perdew and Y. Wang, Phys. Rev. B 45, 13244 (1992)).
+// G(rs) = -2A(1 + a1 rs) ln[1 + 1/(2A(b1 rs^1/2 + b2 rs + b3 rs^3/2 + b4 rs^2))] and dG/drs.
+__device__ __forceinline__ void pw92_g(double rs, double srs, double A, double a1, double b1,
+                                       double b2, double b3, double b4, double& g, double& dg) {
+  const double q0 = -2.0 * A * (1.0 + a1 * rs);
+  const double q1 = 2.0 * A * (b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs);
+  const double q1p = A * (b1 / srs + 2.0 * b2 + 3.0 * b3 * srs + 4.0 * b4 * rs);
+  const double lg = log1p(1.0 / q1);
+  g = q0 * lg;
+  dg = -2.0 * A * a1 * lg - q0 * q1p / (q1 * q1 + q1);
+}
+// Locally collinear PW92 at density n and |m| = mu: vbar = (v_up + v_dn)/2, bmag = (v_up - v_dn)/2
+// (the field along m/|m|), ec = n eps_c; zero where n <= 1e-30.
+__device__ void pw92_lc(double n, double mu, double& vbar, double& bmag, double& ec) {
+  vbar = bmag = ec = 0.0;
+  if (!(n > 1e-30)) return;
+  const double rs = cbrt(0.75 / (3.14159265358979323846 * n));
+  const double srs = sqrt(rs);
+  const double z = fmin(fmax(mu / n, 0.0), 1.0);
+  double e0, d0, e1, d1, ma, dma;
+  pw92_g(rs, srs, 0.031091, 0.21370, 7.5957, 3.5876, 1.6382, 0.49294, e0, d0);    // zeta = 0
+  pw92_g(rs, srs, 0.015545, 0.20548, 14.1189, 6.1977, 3.3662, 0.62517, e1, d1);   // zeta = 1
+  pw92_g(rs, srs, 0.016887, 0.11125, 10.357, 3.6231, 0.88026, 0.49671, ma, dma);  // -alpha_c
+  const double ac = -ma, dac = -dma;
+  const double fpp0 = 1.709921;
+  const double fden = 0.5198420997897464;  // 2^(4/3) - 2
+  const double cu = cbrt(1.0 + z), cd = cbrt(1.0 - z);
+  const double f = ((1.0 + z) * cu + (1.0 - z) * cd - 2.0) / fden;
+  const double fp = (4.0 / 3.0) * (cu - cd) / fden;
+  const double z3 = z * z * z, z4 = z3 * z;
+  const double eps = e0 + ac * f * (1.0 - z4) / fpp0 + (e1 - e0) * f * z4;
+  const double drs = d0 * (1.0 - f * z4) + d1 * f * z4 + dac * f * (1.0 - z4) / fpp0;
+  const double dz = 4.0 * z3 * f * (e1 - e0 - ac / fpp0) + fp * (z4 * (e1 - e0) + (1.0 - z4) * ac / fpp0);
+  vbar = eps - rs / 3.0 * drs - z * dz;
+  bmag = dz;
+  ec = n * eps;
+}
+
 __global__ __launch_bounds__(256) void k_fields(const double* __restrict__ rho,
                                                 const double* __restrict__ vext,
                                                 const double* __restrict__ vH, int xc, double thr,
@@ -670,9 +708,19 @@ __global__ __launch_bounds__(256) void k_fields(const double* __restrict__ rho,
       const double cu = cbrt(nu), cd = cbrt(nd);
       vbar = -0.5 * c * (cu + cd);
       ex = -0.75 * c * (nu * cu + nd * cd);
+      double bmag = 0.0;
       if (mu >= thr) {
         const double den = cu * cu + cu * cd + cd * cd;
-        const double bmag = den > 0.0 ? -0.5 * c * (nu - nd) / den : 0.0;
+        bmag = den > 0.0 ? -0.5 * c * (nu - nd) / den : 0.0;
+      }
+      if (xc >= 2) {
+        double vc, bc, ec;
+        pw92_lc(n, mu, vc, bc, ec);
+        vbar += vc;
+        ex += ec;
+        if (mu >= thr) bmag += bc;
+      }
+      if (mu >= thr) {
         const double s = bmag / mu;
         bx = s * mx;
         by = s * my;

@@ -241,6 +241,22 @@ def localized_product_spinors(rng, S: int, n, L, sigma_env: float, tilt_deg: flo
     return psi
 
 
+def localized_full_spinors(rng, S: int, n, L, sigma_env: float) -> np.ndarray:
+    """Both spinor components random, in a Gaussian envelope of width sigma_env about the cell
+    centre, orthonormalised in FP64: generic local polarisation (0 < zeta < 1) with density tails
+    that reach large rs."""
+    N = int(np.prod(n))
+    dV = float(np.prod(L)) / N
+    env = np.ones(tuple(n))
+    for d in range(3):
+        x = np.arange(n[d]) * (L[d] / n[d]) - 0.5 * L[d]
+        sh = [1, 1, 1]
+        sh[d] = n[d]
+        env = env * np.exp(-0.5 * (x / sigma_env) ** 2).reshape(sh)
+    z = (_smooth_noise(rng, 2 * S, n, L) * env[None]).reshape(S, 2 * N)
+    return _orthonormal_columns(z, dV).reshape((S, 2) + tuple(n))
+
+
 def central_positions(rng, natoms: int, L, radius: float, min_sep: float) -> np.ndarray:
     """Atoms uniform in a ball of the given radius about the cell centre, pairwise >= min_sep."""
     c = 0.5 * np.asarray(L, dtype=np.float64)
@@ -302,7 +318,8 @@ def make_system(n=(8, 8, 8), L=(6.0, 6.0, 6.0), nstates=4, natoms=0, case=7,
                 full_spinors=True, bfield: Optional[BField] = None, dt=0.05,
                 nsteps=4, xc=1, hartree=1, min_sep=None, name="custom",
                 depth_range=(1.0, 3.0), width=1.0, taylor_order=4,
-                laser: Optional[List[LaserPulse]] = None, localized: Optional[float] = None) -> Workload:
+                laser: Optional[List[LaserPulse]] = None, localized: Optional[float] = None,
+                localized_full: bool = False) -> Workload:
     """A seeded system of arbitrary (small) shape, for tests."""
     r_pos, r_depth, r_states, _ = _rngs(case)
     n = tuple(int(v) for v in n)
@@ -318,7 +335,9 @@ def make_system(n=(8, 8, 8), L=(6.0, 6.0, 6.0), nstates=4, natoms=0, case=7,
     depths = r_depth.uniform(depth_range[0], depth_range[1], max(natoms, 0))
     widths = np.full(max(natoms, 0), width)
     v_ext = gaussian_local_potential(n, L, pos, depths, widths)
-    if localized is not None:
+    if localized is not None and localized_full:
+        psi0 = localized_full_spinors(r_states, nstates, n, L, localized)
+    elif localized is not None:
         psi0 = localized_product_spinors(r_states, nstates, n, L, localized)
     elif full_spinors:
         psi0 = random_spinors_full(r_states, nstates, n, L)
