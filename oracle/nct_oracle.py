@@ -18,6 +18,9 @@ Sources (paper arXiv 2506.21908, "Spin non-collinear real-time TDDFT ... INQ"):
   * Kleinman-Bylander + spin-orbit projectors    Eqs. (Vps), (Vps-soc), spinor harmonics, Sec. 3.5
   * Hartree potential                            Eq. (KSpot)
   * uniform electric (laser) pulse               Sec. 4.7, pulse profile of Figs. (fe2-laser), (fe6-laser)
+  * k-point sampling (state index i = (n, k))    Sec. 2.1 (Eq. KSDFT), Sec. 5; states are held as
+    the periodic parts u of psi = exp(i k.r) u, kinetic 1/2 |G + k|^2, projector
+    Bloch phases exp(-/+ i k.d) on the sphere points; k-weights enter the occupations
 The paper names no propagator, Taylor order, Poisson solver or LDA
 parametrisation; the readings taken here are listed in the design doc and below:
   * propagator: enforced time-reversal symmetry (ETRS) with a truncated Taylor
@@ -91,8 +94,19 @@ def ifft3(f):
 # ----------------------------------------------------------------------------
 # kinetic energy:  -1/2 nabla^2  is  1/2 |G|^2  in the plane-wave basis (Eq. TDSDFT)
 # ----------------------------------------------------------------------------
-def kinetic(psi: np.ndarray, grid: Grid) -> np.ndarray:
-    return ifft3(0.5 * grid.g2() * fft3(psi))
+def kinetic(psi: np.ndarray, grid: Grid, kvec: Optional[np.ndarray] = None) -> np.ndarray:
+    """T psi = IFFT(1/2 |G|^2 FFT psi); with Bloch vectors kvec[S, 3] (psi holding the periodic
+    parts u_i of psi_i = exp(i k_i.r) u_i) the factor is 1/2 |G + k_i|^2."""
+    if kvec is None:
+        return ifft3(0.5 * grid.g2() * fft3(psi))
+    out = np.empty_like(psi)
+    G = [grid.gvec(d) for d in range(3)]
+    for i in range(psi.shape[0]):
+        k = kvec[i]
+        g2 = ((G[0] + k[0])[:, None, None] ** 2 + (G[1] + k[1])[None, :, None] ** 2
+              + (G[2] + k[2])[None, None, :] ** 2)
+        out[i] = ifft3(0.5 * g2 * fft3(psi[i]))
+    return out
 
 
 # ----------------------------------------------------------------------------
@@ -393,6 +407,7 @@ class AtomProjectors:
     idx: np.ndarray        # [Ns] flat grid indices (C order) inside the sphere
     beta: np.ndarray       # [P, 2, Ns] complex projector values
     energy: np.ndarray     # [P] KB energies
+    disp: np.ndarray = None  # [Ns, 3] minimum-image displacement r - R_a of each sphere point
 
 
 def build_projectors(grid: Grid, positions: np.ndarray, channels: Sequence,
@@ -428,28 +443,49 @@ def build_projectors(grid: Grid, positions: np.ndarray, channels: Sequence,
                 b = np.stack([f * c_up * ylm(l, m_up, u), f * c_dn * ylm(l, m_dn, u)])
                 betas.append(b)
                 energies.append(energy)
-        out.append(AtomProjectors(sel, np.array(betas), np.array(energies, dtype=np.float64)))
+        out.append(AtomProjectors(sel, np.array(betas), np.array(energies, dtype=np.float64), dd.copy()))
     return out
 
 
-def projections(psi: np.ndarray, projs: List[AtomProjectors], grid: Grid):
-    """C_{a,p,i} = dV sum_{r in sphere a} sum_s conj(beta_{a,p}(r,s)) psi_i(r,s)."""
+def _bloch_phase(ap: AtomProjectors, kvec: Optional[np.ndarray], S: int):
+    """[S, Ns] exp(i k_i.d) for the sphere points of one atom (ones without Bloch vectors)."""
+    if kvec is None:
+        return None
+    return np.exp(1j * (kvec @ ap.disp.T))
+
+
+def projections(psi: np.ndarray, projs: List[AtomProjectors], grid: Grid,
+                kvec: Optional[np.ndarray] = None):
+    """C_{a,p,i} = dV sum_{r in sphere a} sum_s conj(beta_{a,p}(r,s)) psi_i(r,s).
+
+    For Bloch states psi_i = exp(i k_i.r) u_i held as u_i, the sphere about the atom image at
+    R_a + L sees exp(i k_i.(R_a + L + d)) u_i(r): up to the factor exp(i k_i.(R_a + L)), which
+    cancels between the projection and the scatter, C uses exp(i k_i.d) u_i(r)."""
     S = psi.shape[0]
     flat = psi.reshape(S, 2, -1)
     out = []
     for ap in projs:
         sub = flat[:, :, ap.idx]                        # [S, 2, Ns]
+        ph = _bloch_phase(ap, kvec, S)
+        if ph is not None:
+            sub = sub * ph[:, None, :]
         out.append(grid.dV * np.einsum("psk,isk->pi", ap.beta.conj(), sub))
     return out
 
 
-def apply_nonlocal(psi: np.ndarray, projs: List[AtomProjectors], grid: Grid) -> np.ndarray:
-    """V_NL psi_i = sum_a sum_p beta_{a,p} E_{a,p} C_{a,p,i}   (Eqs. Vps, Vps-soc)."""
+def apply_nonlocal(psi: np.ndarray, projs: List[AtomProjectors], grid: Grid,
+                   kvec: Optional[np.ndarray] = None) -> np.ndarray:
+    """V_NL psi_i = sum_a sum_p beta_{a,p} E_{a,p} C_{a,p,i}   (Eqs. Vps, Vps-soc);
+    for Bloch states the scattered rows carry exp(-i k_i.d)."""
     S = psi.shape[0]
     out = np.zeros((S, 2, grid.N), dtype=np.complex128)
-    for ap, C in zip(projs, projections(psi, projs, grid)):
+    for ap, C in zip(projs, projections(psi, projs, grid, kvec)):
         ec = ap.energy[:, None] * C                     # [P, S]
-        out[:, :, ap.idx] += np.einsum("psk,pi->isk", ap.beta, ec)
+        add = np.einsum("psk,pi->isk", ap.beta, ec)
+        ph = _bloch_phase(ap, kvec, S)
+        if ph is not None:
+            add = add * ph.conj()[:, None, :]
+        out[:, :, ap.idx] += add
     return out.reshape(psi.shape)
 
 
@@ -481,6 +517,7 @@ class System:
     dt: float = 0.05
     K: int = 4
     laser: LaserSpec = field(default_factory=LaserSpec)
+    kvec: Optional[np.ndarray] = None   # [S, 3] Bloch vector of each state (None: Gamma only)
 
 
 @dataclass
@@ -519,9 +556,9 @@ def fields_from_density(sysd: System, rho_v: np.ndarray, t: float) -> Fields:
 
 def apply_hamiltonian(sysd: System, psi: np.ndarray, F: Fields) -> np.ndarray:
     """H psi = T psi + [v + b.sigma] psi + V_NL psi  (Eq. TDSDFT with the pseudopotential of Eq. Vps)."""
-    out = kinetic(psi, sysd.grid) + apply_local(psi, F.v, F.b)
+    out = kinetic(psi, sysd.grid, sysd.kvec) + apply_local(psi, F.v, F.b)
     if sysd.projs:
-        out = out + apply_nonlocal(psi, sysd.projs, sysd.grid)
+        out = out + apply_nonlocal(psi, sysd.projs, sysd.grid, sysd.kvec)
     return out
 
 
@@ -576,12 +613,12 @@ def observables(sysd: System, psi: np.ndarray, t: float) -> np.ndarray:
     Ne = n.sum() * dV
     M = m.reshape(3, -1).sum(axis=1) * dV
     f = sysd.occ
-    Tpsi = kinetic(psi, grid)
+    Tpsi = kinetic(psi, grid, sysd.kvec)
     ekin = float(np.sum(f * np.real(np.sum(psi.conj() * Tpsi, axis=(1, 2, 3, 4)))) * dV)
     eloc = float(np.sum((sysd.v_ext + F.vE) * n) * dV)
     enl = 0.0
     if sysd.projs:
-        for ap, C in zip(sysd.projs, projections(psi, sysd.projs, grid)):
+        for ap, C in zip(sysd.projs, projections(psi, sysd.projs, grid, sysd.kvec)):
             enl += float(np.sum(f[None, :] * ap.energy[:, None] * np.abs(C) ** 2))
     eh = float(0.5 * np.sum(F.vH * n) * dV)
     exc = float(np.sum(F.ex) * dV)

@@ -620,6 +620,89 @@ def test_charge_conserved_and_collinear_limit():
     assert np.allclose(obs[:, 2:4], 0, atol=1e-14)
 
 
+# ---------------------------------------------------------------- k-points (Sec. 2.1, Sec. 5)
+def test_bloch_free_electron_exact_phase():
+    """u = const with Bloch vector k: H_k u = |k|^2/2 u, so each half step multiplies by
+    T_4(-i |k|^2 dt/4) exactly (no potential, no XC)."""
+    grid = O.Grid((8, 8, 8), (5.0, 6.0, 7.0))
+    sysd = _free_system(grid.n, grid.L, dt=0.07)
+    k = np.array([0.31, -0.44, 0.27])
+    sysd.kvec = k[None, :]
+    psi0 = np.zeros((1, 2) + grid.n, complex)
+    psi0[0, 0] = 0.6 / math.sqrt(grid.volume)
+    psi0[0, 1] = 0.8j / math.sqrt(grid.volume)
+    eps = 0.5 * float(k @ k)
+    g = _taylor_scalar(-1j * eps * 0.035, 4)
+    psi = psi0
+    for nstep in range(5):
+        psi = O.etrs_step(sysd, psi, 0.07 * nstep)
+        assert np.allclose(psi, psi0 * g ** (2 * (nstep + 1)), atol=1e-14)
+
+
+def _kpoint_primitive(lam=0.05):
+    return I.make_system(n=(12, 12, 12), L=(6.0, 6.0, 6.0), nstates=2, natoms=1, case=48,
+                         lambda_so=lam, full_spinors=True, dt=0.04)
+
+
+def test_supercell_gamma_equals_two_kpoints():
+    """A 2x1x1 supercell at Gamma holding the states exp(i k.r) u_k (k = 0 and pi/L_x, tiled, with
+    1/sqrt 2) evolves exactly as the primitive cell sampled at those two k-points with weights
+    1/2: kinetic |G + k|^2, projector Bloch phases, k-weighted density, Hartree and exchange."""
+    w = _kpoint_primitive()
+    prim = O.system_from_workload(w)
+    Lx = w.L[0]
+    kx = math.pi / Lx
+    S = w.nstates
+    u = np.concatenate([w.psi0, np.roll(w.psi0[::-1], 3, axis=-1)])   # 2S periodic parts
+    kv = np.zeros((2 * S, 3))
+    kv[S:, 0] = kx
+    prim.kvec = kv
+    prim.occ = np.full(2 * S, 0.5)
+    sup_grid = O.Grid((24, 12, 12), (2 * Lx, 6.0, 6.0))
+    pos = np.concatenate([w.positions, w.positions + np.array([Lx, 0, 0])])
+    sup = O.System(grid=sup_grid, occ=np.ones(2 * S), v_ext=np.concatenate([w.v_ext, w.v_ext], axis=0),
+                   projs=O.build_projectors(sup_grid, pos, w.channels, w.r_sphere),
+                   bfield=prim.bfield, xc=1, hartree=1, dt=w.dt, K=4)
+    x = sup_grid.axis(0)
+    def to_super(uu):
+        big = np.concatenate([uu, uu], axis=2) / math.sqrt(2.0)
+        ph = np.exp(1j * np.outer(kv[:, 0], x))                   # [2S, 24]
+        return big * ph[:, None, :, None, None]
+    psi_s = to_super(u)
+    psi_p = u
+    for n in range(2):
+        psi_s = O.etrs_step(sup, psi_s, n * w.dt)
+        psi_p = O.etrs_step(prim, psi_p, n * w.dt)
+    assert np.max(np.abs(psi_s - to_super(psi_p))) < 1e-12 * np.max(np.abs(psi_s))
+    obs_s = O.observables(sup, psi_s, 2 * w.dt)
+    obs_p = O.observables(prim, psi_p, 2 * w.dt)
+    # per-cell quantities: the supercell holds two cells
+    assert np.allclose(obs_s[1:12], 2 * obs_p[1:12], rtol=1e-11, atol=1e-12)
+
+
+def test_projector_bloch_phase_shift_by_reciprocal_vector():
+    """(u, k) and (exp(-i G0.r) u, k + G0) are the same Bloch state, so V_NL must map them to
+    results related by the same factor: the projector phases use the displacement from the atom,
+    and the atom position and image drop out.  (The kinetic term is pinned by the free-electron
+    and supercell tests; on a finite FFT grid a shift by G0 wraps the highest frequencies.)"""
+    w = _kpoint_primitive()
+    sysd = O.system_from_workload(w)
+    k = np.tile(np.array([0.2, -0.3, 0.45]), (w.nstates, 1))
+    G0 = 2 * math.pi * np.array([1, -2, 1]) / np.array(w.L)
+    X, Y, Z = np.meshgrid(*[sysd.grid.axis(d) for d in range(3)], indexing="ij")
+    ph = np.exp(-1j * (G0[0] * X + G0[1] * Y + G0[2] * Z))
+    a = O.apply_nonlocal(w.psi0, sysd.projs, sysd.grid, k)
+    b = O.apply_nonlocal(w.psi0 * ph, sysd.projs, sysd.grid, k + G0)
+    assert np.max(np.abs(a)) > 1e-3
+    assert np.max(np.abs(b - a * ph)) < 1e-13 * np.max(np.abs(a))
+    # and V_NL stays Hermitian with Bloch phases
+    x = w.psi0
+    y = np.roll(w.psi0, 2, axis=-1)
+    lhs = np.vdot(x, O.apply_nonlocal(y, sysd.projs, sysd.grid, k))
+    rhs = np.vdot(O.apply_nonlocal(x, sysd.projs, sysd.grid, k), y)
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+
 # ---------------------------------------------------------------- laser (Sec. 4.7)
 def _laser_packet_system(dt, E0):
     grid = O.Grid((28, 28, 40), (14.0, 14.0, 20.0))   # packet tails negligible at the faces
