@@ -23,7 +23,7 @@ METRIC = "TDDFT steps/s + Hψ HBM GB/s, FP64 vs FP32-mixed; adjoint/forward time
 HBM_PEAK_GBS = 8000.0
 XC_NAMES = {0: "none", 1: "Slater exchange, locally collinear",
             2: "Slater exchange + PW92 correlation (LSDA), locally collinear"}
-WORKLOADS = {"tiny": 0, "cluster": 1, "solid": 2, "grad": 3, "large": 4, "laser": 5}
+WORKLOADS = {"tiny": 0, "cluster": 1, "solid": 2, "grad": 3, "large": 4, "laser": 5, "kpoints": 6}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2506_21908_amd", "csrc", "nct_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "plane_stage_cluster48_fp64_traffic.md")
 

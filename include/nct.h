@@ -155,6 +155,15 @@ typedef struct {
  * a non-finite parameter. */
 nct_status nct_set_laser(nct_system *sys, int npulses, const nct_laser_pulse *pulses);
 
+/* k-point sampling (the state index i = (n, k) of Eq. KSDFT; Sec. 5 runs 8 k-points of a bcc
+ * supercell).  kvec host double [nstates][3]: the Bloch vector of each state (bohr^-1, copied);
+ * the states then hold the periodic parts u_i of psi_i = exp(i k_i.r) u_i: the kinetic factor
+ * becomes 1/2 |G + k_i|^2 and the projector rows carry exp(i k_i.d) on projection and
+ * exp(-i k_i.d) on scatter (d the grid point's displacement from the atom).  The k-point weights
+ * enter through params.occ (f_i w_k).  NULL returns to Gamma only.  Synchronises the stream.
+ * Errors: NCT_ERR_ARG for a non-finite component. */
+nct_status nct_set_kpoints(nct_system *sys, const double *kvec);
+
 /* Set the potentials of Eq. (HNC-SDFT):
  *   v_ext_dev  device double [N]: external local potential v_ext(r) (copied), or NULL to keep;
  *   b          host: B_ext(t) description (copied), or NULL to keep;

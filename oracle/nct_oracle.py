@@ -742,4 +742,5 @@ def system_from_workload(w, dt: Optional[float] = None) -> System:
                        for p in getattr(w, "laser", [])])
     return System(grid=grid, occ=np.asarray(w.occ, dtype=np.float64), v_ext=w.v_ext,
                   projs=projs, bfield=bf, xc=w.xc, hartree=w.hartree, thr=w.m_threshold,
-                  dt=w.dt if dt is None else dt, K=w.taylor_order, laser=laser)
+                  dt=w.dt if dt is None else dt, K=w.taylor_order, laser=laser,
+                  kvec=None if getattr(w, "kvec", None) is None else np.asarray(w.kvec, dtype=np.float64))

@@ -77,6 +77,13 @@ struct nct_system {
   double* g2yz64 = nullptr;
   float* g2x32 = nullptr;
   float* g2yz32 = nullptr;
+  // signed G per axis (x digit-reversed, y and z per position of the transformed yz plane)
+  double *gsx64 = nullptr, *gsy64 = nullptr, *gsz64 = nullptr;
+  float *gsx32 = nullptr, *gsy32 = nullptr, *gsz32 = nullptr;
+  // Bloch vectors [S][3] of the states (k-point sampling); null: Gamma only
+  double* kv64 = nullptr;
+  float* kv32 = nullptr;
+  bool has_k = false;
 
   // device: fields and densities (FP64)
   double* occ = nullptr;
@@ -379,6 +386,7 @@ nct_status build_projectors(nct_system* s) {
   std::vector<int> pidx;
   std::vector<int> ix_of_row;
   std::vector<std::complex<double>> beta;  // [J][2][PP]
+  std::vector<R> disp;                      // [J][3]
   std::vector<double> energy(size_t(s->natoms) * PP, 0.0);
   std::vector<double> rnorm(p.nchannels);
   for (int c = 0; c < p.nchannels; ++c) rnorm[c] = radial_norm(p.channels[c].l, p.channels[c].rc, rs);
@@ -401,6 +409,7 @@ nct_status build_projectors(nct_system* s) {
           }
           pidx.push_back(iy * NZ + iz);
           ix_of_row.push_back(ix);
+          for (int k = 0; k < 3; ++k) disp.push_back(R(d[k]));
           std::vector<std::complex<double>> rowv(2 * PP, std::complex<double>(0, 0));
           int pcount = 0;
           for (int c = 0; c < p.nchannels; ++c) {
@@ -464,6 +473,9 @@ nct_status build_projectors(nct_system* s) {
   }
   R* d_beta;
   if ((r = upload(s, braw, &d_beta)) != NCT_OK) return r;
+  R* d_disp;
+  if ((r = upload(s, disp, &d_disp)) != NCT_OK) return r;
+  pt.disp = d_disp;
   pt.row_off = d_row_off;
   pt.pidx = d_pidx;
   pt.pr_off = d_pr_off;
@@ -544,6 +556,19 @@ struct Engine {
   const void* twz() const { return sizeof(R) == 8 ? s->tw64[2] : s->tw32[2]; }
   const R* g2x() const { return sizeof(R) == 8 ? (const R*)s->g2x64 : (const R*)s->g2x32; }
   const R* g2yz() const { return sizeof(R) == 8 ? (const R*)s->g2yz64 : (const R*)s->g2yz32; }
+  const R* kvR() const {
+    if (!s->has_k) return nullptr;
+    return sizeof(R) == 8 ? (const R*)s->kv64 : (const R*)s->kv32;
+  }
+  KTables<R> ktab(int state_off = 0) const {
+    KTables<R> k;
+    k.gx = sizeof(R) == 8 ? (const R*)s->gsx64 : (const R*)s->gsx32;
+    k.gy = sizeof(R) == 8 ? (const R*)s->gsy64 : (const R*)s->gsy32;
+    k.gz = sizeof(R) == 8 ? (const R*)s->gsz64 : (const R*)s->gsz32;
+    k.kv = kvR();
+    k.state_off = state_off;
+    return k;
+  }
   const R* fieldsR() const { return sizeof(R) == 8 ? (const R*)s->fields : (const R*)s->fields32; }
   double psiB() const { return 2.0 * s->S * double(s->N) * sizeof(R) * 2; }
   double rowsB() const { return 2.0 * s->S * double(s->pt.Jtot) * sizeof(R) * 2; }
@@ -645,7 +670,7 @@ struct Engine {
   nct_status xpass(const void* src, void* dst) {
     return check(timed(s, NCT_K_XPASS, 2 * psiB(), 0, [&] {
                    return launch_xpass<R>(s->n, 2 * s->S, src, dst, g2x(), g2yz(), R(0.5 / double(s->N)),
-                                          0, twx(), s->st, s->cache_mode); }), "xpass");
+                                          0, twx(), s->st, s->cache_mode, ktab()); }), "xpass");
   }
 
   nct_status plane_stage(const StageArgs<R>& sa) {
@@ -730,7 +755,7 @@ struct Engine {
       void* dst = kin_dst ? kin_dst : s->tmp;
       if ((r = check(timed_on(s, g.st, NCT_K_XPASS, 2 * psiB() * frac, 0, [&] {
              return launch_xpass<R>(s->n, 2 * g.S, offs(chat, g.i0), offs(dst, g.i0), g2x(), g2yz(),
-                                    R(0.5 / double(s->N)), 0, twx(), g.st, s->cache_mode); }), "xpass")) != NCT_OK)
+                                    R(0.5 / double(s->N)), 0, twx(), g.st, s->cache_mode, ktab(g.i0)); }), "xpass")) != NCT_OK)
         return r;
     }
     if (s->natoms) HIPCHK(s, hipStreamWaitEvent(g.st, g.ev_proj, 0));
@@ -743,6 +768,7 @@ struct Engine {
     sa.acc = offs(sa.acc, g.i0);
     sa.Y = s->natoms ? offr(s->Y, g.i0) : nullptr;
     sa.W = offr(sa.W, g.i0);
+    sa.state_off = g.i0;
     double b = psiB();
     if (sa.w_in) b += psiB();
     if (sa.x_base && sa.x_base != sa.w_in) b += psiB();
@@ -771,6 +797,7 @@ struct Engine {
     const void* cW = xW;
     StageArgs<R> sa;
     sa.cache_mode = s->cache_mode;
+    sa.kv = kvR();
     externals(t, sa);
     sa.fields = fieldsR();
     nct_status r;
@@ -806,7 +833,7 @@ struct Engine {
   nct_status prepare(const void* psi, void* hat, void* W) {
     return check(timed(s, NCT_K_PLANE_FWD, 2 * psiB() + (s->natoms ? rowsB() : 0.0), 0, [&] {
                    return launch_plane_fwd<R>(s->n, 2 * s->S, psi, hat, s->natoms ? W : nullptr, &s->pt,
-                                              twy(), twz(), s->st); }), "plane_fwd");
+                                              twy(), twz(), s->st, kvR()); }), "plane_fwd");
   }
 
   nct_status obs_row(double t, double* row) {
@@ -814,7 +841,7 @@ struct Engine {
     int ntiles = 0;
     if ((r = check(timed(s, NCT_K_OBS, psiB(), 0, [&] {
            return launch_xpass_energy<R>(s->n, 2 * s->S, s->psihat, g2x(), g2yz(), R(0.5 / double(s->N)),
-                                         twx(), s->epart, &ntiles, s->st); }), "energy")) != NCT_OK)
+                                         twx(), s->epart, &ntiles, s->st, ktab()); }), "energy")) != NCT_OK)
       return r;
     if (s->natoms) {
       if ((r = contract(s->Wpsi, s->st)) != NCT_OK) return r;
@@ -969,6 +996,7 @@ struct Engine {
     if ((r = prepare(lam_out, s->tmp, s->Wwork)) != NCT_OK) return r;
     StageArgs<R> sa;
     sa.cache_mode = s->cache_mode;
+    sa.kv = kvR();
     externals(t, sa);
     sa.fields = fieldsR();
     const void* cur = lam_out;
@@ -1096,6 +1124,7 @@ struct Engine {
     if ((r = join_projections()) != NCT_OK) return r;
     StageArgs<R> sa;
     sa.cache_mode = s->cache_mode;
+    sa.kv = kvR();
     externals(t, sa);
     sa.fields = fieldsR();
     sa.tmp_in = s->tmp;
@@ -1145,6 +1174,20 @@ nct_status build_fft_tables(nct_system* s) {
       const double g2 = gval(kz[j], s->n[2], s->prm.cell[2]);
       gyz[size_t(i) * s->n[2] + j] = g1 * g1 + g2 * g2;
     }
+  std::vector<double> sx(s->n[0]), sy(size_t(s->n[1]) * s->n[2]), sz(size_t(s->n[1]) * s->n[2]);
+  for (int i = 0; i < s->n[0]; ++i) sx[i] = gval(kx[i], s->n[0], s->prm.cell[0]);
+  for (int i = 0; i < s->n[1]; ++i)
+    for (int j = 0; j < s->n[2]; ++j) {
+      sy[size_t(i) * s->n[2] + j] = gval(ky[i], s->n[1], s->prm.cell[1]);
+      sz[size_t(i) * s->n[2] + j] = gval(kz[j], s->n[2], s->prm.cell[2]);
+    }
+  std::vector<float> sx32(sx.begin(), sx.end()), sy32(sy.begin(), sy.end()), sz32(sz.begin(), sz.end());
+  if ((r = upload(s, sx, &s->gsx64)) != NCT_OK) return r;
+  if ((r = upload(s, sy, &s->gsy64)) != NCT_OK) return r;
+  if ((r = upload(s, sz, &s->gsz64)) != NCT_OK) return r;
+  if ((r = upload(s, sx32, &s->gsx32)) != NCT_OK) return r;
+  if ((r = upload(s, sy32, &s->gsy32)) != NCT_OK) return r;
+  if ((r = upload(s, sz32, &s->gsz32)) != NCT_OK) return r;
   std::vector<float> gx32(gx.begin(), gx.end()), gyz32(gyz.begin(), gyz.end());
   if ((r = upload(s, gx, &s->g2x64)) != NCT_OK) return r;
   if ((r = upload(s, gyz, &s->g2yz64)) != NCT_OK) return r;
@@ -1368,6 +1411,31 @@ void nct_destroy_system(nct_system* sys) {
 
 const char* nct_last_error(const nct_system* sys) {
   return sys ? sys->err.c_str() : g_create_error.c_str();
+}
+
+nct_status nct_set_kpoints(nct_system* s, const double* kvec) {
+  if (!s) return NCT_ERR_ARG;
+  if (!kvec) {
+    s->has_k = false;
+    return NCT_OK;
+  }
+  const size_t n = size_t(s->S) * 3;
+  for (size_t k = 0; k < n; ++k)
+    if (!std::isfinite(kvec[k])) return fail(s, NCT_ERR_ARG, "non-finite Bloch vector component %zu", k);
+  nct_status r;
+  if (!s->kv64) {
+    void* p;
+    if ((r = dalloc(s, n * sizeof(double), &p)) != NCT_OK) return r;
+    s->kv64 = static_cast<double*>(p);
+    if ((r = dalloc(s, n * sizeof(float), &p)) != NCT_OK) return r;
+    s->kv32 = static_cast<float*>(p);
+  }
+  std::vector<float> k32(kvec, kvec + n);
+  HIPCHK(s, hipMemcpyAsync(s->kv64, kvec, n * sizeof(double), hipMemcpyHostToDevice, s->st));
+  HIPCHK(s, hipMemcpyAsync(s->kv32, k32.data(), n * sizeof(float), hipMemcpyHostToDevice, s->st));
+  HIPCHK(s, hipStreamSynchronize(s->st));
+  s->has_k = true;
+  return NCT_OK;
 }
 
 nct_status nct_set_laser(nct_system* s, int npulses, const nct_laser_pulse* pulses) {

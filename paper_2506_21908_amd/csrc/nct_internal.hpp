@@ -26,6 +26,7 @@ struct ProjTables {
   const int* pr_begin = nullptr;  // [nranges]
   const int* pr_end = nullptr;    // [nranges]
   const void* beta = nullptr;     // complex R [Jtot][2][PP]
+  const void* disp = nullptr;     // R [Jtot][3]: displacement of each sphere row from its atom
   const double* energy = nullptr; // [natoms][PP] (0 beyond P)
 };
 
@@ -47,6 +48,21 @@ struct StageArgs {
   void* acc = nullptr;
   // cache policy of the state-sized operands: 0 plain, 1 streaming stores, 2 streaming loads too
   int cache_mode = 0;
+  // Bloch vectors [S][3] of the states (null: Gamma only); this launch's state 0 is state_off
+  const R* kv = nullptr;
+  int state_off = 0;
+};
+
+// Kinetic factor with Bloch vectors: |G + k|^2 from signed per-axis G tables (gx in the
+// digit-reversed x order of the column transforms, gy / gz per position of the 2D-transformed yz
+// plane).  kv null: the |G|^2 tables are used instead (Gamma only).
+template <typename R>
+struct KTables {
+  const R* gx = nullptr;
+  const R* gy = nullptr;
+  const R* gz = nullptr;
+  const R* kv = nullptr;   // [S][3]
+  int state_off = 0;       // state of batch entries 0, 1
 };
 
 // Launchers (return hipError_t of the launch).  n = {NX, NY, NZ}.
@@ -55,9 +71,11 @@ hipError_t launch_plane_stage(const int n[3], int S, const StageArgs<R>& a, cons
                               const void* twy, const void* twz, hipStream_t st);
 // Forward 2D transform of B planes-sets (batch entries, each [NX][NY][NZ]); optionally gathers
 // sphere rows of the input into W (batch must then be 2S in state/spinor order).
+// With kv (Bloch vectors [S][3]) the gathered rows carry exp(i k.d) (state of entry b = b / 2).
 template <typename R>
 hipError_t launch_plane_fwd(const int n[3], int B, const void* in, void* out, void* W,
-                            const ProjTables* pt, const void* twy, const void* twz, hipStream_t st);
+                            const ProjTables* pt, const void* twy, const void* twz, hipStream_t st,
+                            const R* kv = nullptr);
 // Inverse 2D transform; out = scale * result.
 template <typename R>
 hipError_t launch_plane_inv(const int n[3], int B, const void* in, void* out, R scale,
@@ -68,13 +86,13 @@ hipError_t launch_plane_inv(const int n[3], int B, const void* in, void* out, R 
 template <typename R>
 hipError_t launch_xpass(const int n[3], int B, const void* src, void* dst, const R* g2x,
                         const R* g2yz, R kscale, int mode, const void* twx, hipStream_t st,
-                        int cache_mode = 0);
+                        int cache_mode = 0, KTables<R> kt = KTables<R>{});
 // Energy pass: per (batch, tile) partial sums of sum kscale*G^2 |X|^2 and sum |X|^2 of the full
 // 3D transform (input in the 2D-transformed form).  part: [B][ntiles][2] doubles.
 template <typename R>
 hipError_t launch_xpass_energy(const int n[3], int B, const void* src, const R* g2x,
                                const R* g2yz, R kscale, const void* twx, double* part,
-                               int* ntiles_out, hipStream_t st);
+                               int* ntiles_out, hipStream_t st, KTables<R> kt = KTables<R>{});
 
 template <typename R>
 hipError_t launch_density(const void* psi, const double* occ, int S, size_t N, double* rho,

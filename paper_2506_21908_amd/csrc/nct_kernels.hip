@@ -80,6 +80,19 @@ __device__ __forceinline__ void st_stream(cpx<R>* p, cpx<R> v) {
   }
 }
 
+// Bloch phase exp(i q.d) of one sphere row (q: Bloch vector, d: the row's displacement from its
+// atom).  Rows gathered for the projections carry it, scattered rows its conjugate.
+__device__ __forceinline__ cpx<double> bloch_phase(const double* q, const double* d) {
+  double sn, cs;
+  sincos(q[0] * d[0] + q[1] * d[1] + q[2] * d[2], &sn, &cs);
+  return {cs, sn};
+}
+__device__ __forceinline__ cpx<float> bloch_phase(const float* q, const float* d) {
+  float sn, cs;
+  sincosf(q[0] * d[0] + q[1] * d[1] + q[2] * d[2], &sn, &cs);
+  return {cs, sn};
+}
+
 // ---------------------------------------------------------------- plane pass: fused H stage
 template <typename R, int NY, int NZ, int M>
 __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a, ProjTables pt,
@@ -179,12 +192,15 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a
     }
     __syncthreads();
     const size_t rowbase = size_t(2 * i + s) * pt.Jtot;
+    const R* kq = a.kv ? a.kv + 3 * (a.state_off + i) : nullptr;
+    const R* disp = reinterpret_cast<const R*>(pt.disp);
     if (Y) {
       for (int r = r0; r < r1; ++r) {
         const int jb = pt.pr_begin[r], je = pt.pr_end[r];
         for (int J = jb + tid; J < je; J += NT) {
           const int e = pt.pidx[J];
-          const cpx<R> y = Y[rowbase + J];
+          cpx<R> y = Y[rowbase + J];
+          if (kq) y = cmulc(y, bloch_phase(kq, disp + 3 * J));
           cpx<R>& d = plane[(e / NZ) * PZ + (e % NZ)];
           d.x += a.cre * y.x - a.cim * y.y;
           d.y += a.cre * y.y + a.cim * y.x;
@@ -197,7 +213,9 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a
         const int jb = pt.pr_begin[r], je = pt.pr_end[r];
         for (int J = jb + tid; J < je; J += NT) {
           const int e = pt.pidx[J];
-          Wr[rowbase + J] = plane[(e / NZ) * PZ + (e % NZ)];
+          cpx<R> o = plane[(e / NZ) * PZ + (e % NZ)];
+          if (kq) o = cmul(o, bloch_phase(kq, disp + 3 * J));
+          Wr[rowbase + J] = o;
         }
       }
     }
@@ -374,12 +392,15 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(Stag
   const int r0 = pt.pr_off ? pt.pr_off[x] : 0;
   const int r1 = pt.pr_off ? pt.pr_off[x + 1] : 0;
   const size_t rowbase = size_t(2 * i + h) * pt.Jtot;
+  const R* kq = a.kv ? a.kv + 3 * (a.state_off + i) : nullptr;
+  const R* disp = reinterpret_cast<const R*>(pt.disp);
   if (Y) {
     for (int r = r0; r < r1; ++r) {
       const int jb = pt.pr_begin[r], je = pt.pr_end[r];
       for (int J = jb + th; J < je; J += NTH) {
         const int e = pt.pidx[J];
-        const cpx<R> y = Y[rowbase + J];
+        cpx<R> y = Y[rowbase + J];
+        if (kq) y = cmulc(y, bloch_phase(kq, disp + 3 * J));
         cpx<R>& d = pl[(e / NZ) * PZ + (e % NZ)];
         d.x += a.cre * y.x - a.cim * y.y;
         d.y += a.cre * y.y + a.cim * y.x;
@@ -392,7 +413,9 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(Stag
       const int jb = pt.pr_begin[r], je = pt.pr_end[r];
       for (int J = jb + th; J < je; J += NTH) {
         const int e = pt.pidx[J];
-        Wr[rowbase + J] = pl[(e / NZ) * PZ + (e % NZ)];
+        cpx<R> o = pl[(e / NZ) * PZ + (e % NZ)];
+        if (kq) o = cmul(o, bloch_phase(kq, disp + 3 * J));
+        Wr[rowbase + J] = o;
       }
     }
   }
@@ -430,7 +453,8 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_fwd(const cpx<R>* in
                                                                  cpx<R>* W, ProjTables pt,
                                                                  const cpx<R>* __restrict__ twy_g,
                                                                  const cpx<R>* __restrict__ twz_g,
-                                                                 int B, int NX) {
+                                                                 int B, int NX,
+                                                                 const R* __restrict__ kv) {
   constexpr int NP = NY * NZ;
   constexpr int NT = plane_nt(NP);
   constexpr int PZ = NZ + 1;
@@ -449,10 +473,14 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_fwd(const cpx<R>* in
   __syncthreads();
   if (W && pt.pr_off) {
     const size_t rowbase = size_t(b) * pt.Jtot;
+    const R* kq = kv ? kv + 3 * (b / 2) : nullptr;
+    const R* disp = reinterpret_cast<const R*>(pt.disp);
     for (int r = pt.pr_off[x]; r < pt.pr_off[x + 1]; ++r) {
       for (int J = pt.pr_begin[r] + tid; J < pt.pr_end[r]; J += NT) {
         const int e = pt.pidx[J];
-        W[rowbase + J] = plane[(e / NZ) * PZ + (e % NZ)];
+        cpx<R> o = plane[(e / NZ) * PZ + (e % NZ)];
+        if (kq) o = cmul(o, bloch_phase(kq, disp + 3 * J));
+        W[rowbase + J] = o;
       }
     }
     __syncthreads();
@@ -506,7 +534,7 @@ template <typename R, int NX, int TC, int XT, int M>
 __global__ __launch_bounds__(XP_NT) void k_xpass(const cpx<R>* src, cpx<R>* dst, int NYZ,
                                                  const R* __restrict__ g2x,
                                                  const R* __restrict__ g2yz, R kscale, int mode,
-                                                 const cpx<R>* __restrict__ twx_g) {
+                                                 const cpx<R>* __restrict__ twx_g, KTables<R> kt) {
   __shared__ cpx<R> tile[NX * TC];
   __shared__ cpx<R> tw[NX];
   constexpr int PER = (NX * TC + XP_NT - 1) / XP_NT;
@@ -547,7 +575,16 @@ _Pragma("clang loop unroll(full)")
     for (int j = 0; j < PER; ++j) {
       const int e = tid + j * XP_NT;
       if (e < NX * TC) {
-        const R g = g2x[e / TC] + g2yz[q0 + (e % TC)];
+        R g;
+        if (kt.kv) {  // |G + k|^2 of this spinor component's state
+          const R* k = kt.kv + 3 * (kt.state_off + b / 2);
+          const R gx = kt.gx[e / TC] + k[0];
+          const R gy = kt.gy[q0 + (e % TC)] + k[1];
+          const R gz = kt.gz[q0 + (e % TC)] + k[2];
+          g = gx * gx + gy * gy + gz * gz;
+        } else {
+          g = g2x[e / TC] + g2yz[q0 + (e % TC)];
+        }
         R m;
         if (mode == 0) m = kscale * g;
         else m = g > R(0) ? kscale / g : R(0);
@@ -570,7 +607,7 @@ __global__ __launch_bounds__(XP_NT) void k_xpass_energy(const cpx<R>* src, int N
                                                         const R* __restrict__ g2x,
                                                         const R* __restrict__ g2yz, R kscale,
                                                         const cpx<R>* __restrict__ twx_g,
-                                                        double* part) {
+                                                        double* part, KTables<R> kt) {
   __shared__ cpx<R> tile[NX * TC];
   __shared__ cpx<R> tw[NX];
   __shared__ double red[XP_NT / 64];
@@ -600,7 +637,16 @@ __global__ __launch_bounds__(XP_NT) void k_xpass_energy(const cpx<R>* src, int N
   double s1 = 0.0, s2 = 0.0;
   for (int e = tid; e < NX * TC; e += XP_NT) {
     const int xx = e / TC, c = e - (e / TC) * TC;
-    const double g = double(g2x[xx]) + double(g2yz[q0 + c]);
+    double g;
+    if (kt.kv) {
+      const R* k = kt.kv + 3 * (kt.state_off + b / 2);
+      const double gx = double(kt.gx[xx]) + double(k[0]);
+      const double gy = double(kt.gy[q0 + c]) + double(k[1]);
+      const double gz = double(kt.gz[q0 + c]) + double(k[2]);
+      g = gx * gx + gy * gy + gz * gz;
+    } else {
+      g = double(g2x[xx]) + double(g2yz[q0 + c]);
+    }
     const double a2 = double(tile[e].x) * double(tile[e].x) + double(tile[e].y) * double(tile[e].y);
     s1 += double(kscale) * g * a2;
     s2 += a2;
@@ -1280,7 +1326,8 @@ hipError_t launch_plane_stage(const int n[3], int S, const StageArgs<R>& a, cons
 
 template <typename R>
 hipError_t launch_plane_fwd(const int n[3], int B, const void* in, void* out, void* W,
-                            const ProjTables* pt, const void* twy, const void* twz, hipStream_t st) {
+                            const ProjTables* pt, const void* twy, const void* twz, hipStream_t st,
+                            const R* kv) {
   const unsigned grid = unsigned(B) * unsigned(n[0]);
   ProjTables none;
   const ProjTables& p = pt ? *pt : none;
@@ -1294,7 +1341,7 @@ hipError_t launch_plane_fwd(const int n[3], int B, const void* in, void* out, vo
                        reinterpret_cast<const cpx<R>*>(in), reinterpret_cast<cpx<R>*>(out),  \
                        reinterpret_cast<cpx<R>*>(W), p,                                     \
                        reinterpret_cast<const cpx<R>*>(twy), reinterpret_cast<const cpx<R>*>(twz), \
-                       B, n[0]);                                                            \
+                       B, n[0], kv);                                                        \
     return hipGetLastError();                                                               \
   }
   NCT_PLANE_PAIRS(X)
@@ -1325,7 +1372,8 @@ hipError_t launch_plane_inv(const int n[3], int B, const void* in, void* out, R 
 
 template <typename R, int NX, int TC>
 static hipError_t launch_xpass_tc(int B, int NYZ, const void* src, void* dst, const R* g2x, const R* g2yz,
-                                  R kscale, int mode, const void* twx, int cache_mode, hipStream_t st) {
+                                  R kscale, int mode, const void* twx, int cache_mode, hipStream_t st,
+                                  KTables<R> kt) {
   const int tiles = NYZ / TC;
   const auto s_ = reinterpret_cast<const cpx<R>*>(src);
   const auto d_ = reinterpret_cast<cpx<R>*>(dst);
@@ -1334,25 +1382,25 @@ static hipError_t launch_xpass_tc(int B, int NYZ, const void* src, void* dst, co
   // costs occupancy
   const dim3 grid(unsigned(B) * unsigned(tiles));
   if (cache_mode >= 2)
-    nct_launch((k_xpass<R, NX, TC, 1, 2>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_);
+    nct_launch((k_xpass<R, NX, TC, 1, 2>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_, kt);
   else if (cache_mode == 1)
-    nct_launch((k_xpass<R, NX, TC, 1, 1>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_);
+    nct_launch((k_xpass<R, NX, TC, 1, 1>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_, kt);
   else
-    nct_launch((k_xpass<R, NX, TC, 1, 0>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_);
+    nct_launch((k_xpass<R, NX, TC, 1, 0>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_, kt);
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_xpass(const int n[3], int B, const void* src, void* dst, const R* g2x,
                         const R* g2yz, R kscale, int mode, const void* twx, hipStream_t st,
-                        int cache_mode) {
+                        int cache_mode, KTables<R> kt) {
   const int NYZ = n[1] * n[2];
 #define X(A)                                                                                \
   if (n[0] == A) {                                                                          \
     constexpr int TCP = xpass_tc<R>(A);                                                     \
     if (NYZ % TCP == 0)                                                                     \
-      return launch_xpass_tc<R, A, TCP>(B, NYZ, src, dst, g2x, g2yz, kscale, mode, twx, cache_mode, st); \
-    return launch_xpass_tc<R, A, 16>(B, NYZ, src, dst, g2x, g2yz, kscale, mode, twx, cache_mode, st); \
+      return launch_xpass_tc<R, A, TCP>(B, NYZ, src, dst, g2x, g2yz, kscale, mode, twx, cache_mode, st, kt); \
+    return launch_xpass_tc<R, A, 16>(B, NYZ, src, dst, g2x, g2yz, kscale, mode, twx, cache_mode, st, kt); \
   }
   NCT_LINES(X)
 #undef X
@@ -1362,7 +1410,7 @@ hipError_t launch_xpass(const int n[3], int B, const void* src, void* dst, const
 template <typename R>
 hipError_t launch_xpass_energy(const int n[3], int B, const void* src, const R* g2x,
                                const R* g2yz, R kscale, const void* twx, double* part,
-                               int* ntiles_out, hipStream_t st) {
+                               int* ntiles_out, hipStream_t st, KTables<R> kt) {
   const int NYZ = n[1] * n[2];
 #define X(A)                                                                                \
   if (n[0] == A) {                                                                          \
@@ -1371,12 +1419,12 @@ hipError_t launch_xpass_energy(const int n[3], int B, const void* src, const R* 
       *ntiles_out = NYZ / TCP;                                                              \
       nct_launch((k_xpass_energy<R, A, TCP>), dim3(unsigned(B) * unsigned(NYZ / TCP)), \
                          dim3(XP_NT), 0, st, reinterpret_cast<const cpx<R>*>(src), NYZ, g2x,  \
-                         g2yz, kscale, reinterpret_cast<const cpx<R>*>(twx), part);          \
+                         g2yz, kscale, reinterpret_cast<const cpx<R>*>(twx), part, kt);      \
     } else {                                                                                \
       *ntiles_out = NYZ / 16;                                                               \
       nct_launch((k_xpass_energy<R, A, 16>), dim3(unsigned(B) * unsigned(NYZ / 16)),  \
                          dim3(XP_NT), 0, st, reinterpret_cast<const cpx<R>*>(src), NYZ, g2x,  \
-                         g2yz, kscale, reinterpret_cast<const cpx<R>*>(twx), part);          \
+                         g2yz, kscale, reinterpret_cast<const cpx<R>*>(twx), part, kt);      \
     }                                                                                       \
     return hipGetLastError();                                                               \
   }
@@ -1525,13 +1573,14 @@ hipError_t launch_real_to_cpx(const double* r, size_t N, void* out, hipStream_t 
   template hipError_t launch_plane_stage<R>(const int*, int, const StageArgs<R>&, const ProjTables&, \
                                             const void*, const void*, hipStream_t);                \
   template hipError_t launch_plane_fwd<R>(const int*, int, const void*, void*, void*,              \
-                                          const ProjTables*, const void*, const void*, hipStream_t); \
+                                          const ProjTables*, const void*, const void*, hipStream_t, \
+                                          const R*);                                               \
   template hipError_t launch_plane_inv<R>(const int*, int, const void*, void*, R, const void*,     \
                                           const void*, hipStream_t);                               \
   template hipError_t launch_xpass<R>(const int*, int, const void*, void*, const R*, const R*, R,  \
-                                      int, const void*, hipStream_t, int);                         \
+                                      int, const void*, hipStream_t, int, KTables<R>);             \
   template hipError_t launch_xpass_energy<R>(const int*, int, const void*, const R*, const R*, R,  \
-                                             const void*, double*, int*, hipStream_t);             \
+                                             const void*, double*, int*, hipStream_t, KTables<R>); \
   template hipError_t launch_density<R>(const void*, const double*, int, size_t, double*,          \
                                         hipStream_t);                                              \
   template hipError_t launch_proj_contract<R>(const ProjTables&, const void*, int, double, void*,  \

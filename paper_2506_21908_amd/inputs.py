@@ -111,6 +111,7 @@ class Workload:
     taylor_order: int = 4
     checkpoint_every: int = 0
     laser: List[LaserPulse] = dataclasses.field(default_factory=list)
+    kvec: Optional[np.ndarray] = None   # [S, 3] Bloch vector of each state (None: Gamma only)
 
     @property
     def natoms(self) -> int:
@@ -309,6 +310,13 @@ def bcc_positions(rng, L: float, cells: int = 2, jitter: float = 0.05) -> np.nda
     return np.mod(pos, L)
 
 
+def monkhorst_pack(L, grid=(2, 2, 2)) -> np.ndarray:
+    """Monkhorst-Pack k-points of an orthorhombic cell: k_d = (2 pi / L_d)((2 i + 1 - q_d)/(2 q_d))."""
+    axes = [2.0 * math.pi / L[d] * (2.0 * np.arange(grid[d]) + 1.0 - grid[d]) / (2.0 * grid[d])
+            for d in range(3)]
+    return np.array([[a, b, c] for a in axes[0] for b in axes[1] for c in axes[2]])
+
+
 def circular_pulses(t_centers: Sequence[float], omegas: Sequence[float], A: float, tau: float):
     return [Pulse(A=A, omega=w, t0=t, tau=tau) for t, w in zip(t_centers, omegas)]
 
@@ -360,12 +368,21 @@ def workload(case: int) -> Workload:
     2 solid-like 64^3 x 256, 16 atoms bcc 2x2x2 (+0.05 bohr jitter), circular pulse, 1000 steps
     3 gradient case 32^3 x 32, 2 atoms, 4 circular pulse components, 200 steps, checkpoint 20
     4 large 96^3 x 512, 32 atoms, 4 circular pulse components, 500 steps, checkpoint 25
+    6 k-point solid: the solid-like system of case 2 sampled on a 2x2x2 Monkhorst-Pack grid,
+      8 k-points x 32 states (weights 1/8 in the occupations), the same 256 states in total
     5 laser-driven cluster 48^3 x 64, 4 atoms within 5 bohr of the centre, states in a Gaussian
       envelope (sigma 3.5 bohr) about the centre, z-polarised electric pulse A = 1 a.u.,
       omega = 10 eV, t0 = 0.1 fs, tau = 0.5 fs (the parameters of the paper's cluster runs),
       200 steps
     """
     r_pos, r_depth, r_states, _r_jit = _rngs(case)
+    if case == 6:
+        w = workload(2)
+        nk, per = 8, 32
+        w.name = "kpoints-solid-64^3x8kx32-16x18KB"
+        w.kvec = np.repeat(monkhorst_pack(w.L), per, axis=0)
+        w.occ = np.full(nk * per, 1.0 / nk)
+        return w
     if case == 5:
         n, L, S, natoms = (48, 48, 48), (20.0,) * 3, 64, 4
         pos = central_positions(r_pos, natoms, L, 5.0, 4.2)

@@ -78,6 +78,8 @@ def lib():
         L.nct_set_potentials.restype = c_int
         L.nct_set_laser.argtypes = [c_void_p, c_int, POINTER(LaserPulse)]
         L.nct_set_laser.restype = c_int
+        L.nct_set_kpoints.argtypes = [c_void_p, c_void_p]
+        L.nct_set_kpoints.restype = c_int
         L.nct_density_magnetization.argtypes = [c_void_p, c_void_p, c_double, c_void_p,
                                                 POINTER(c_double), c_int]
         L.nct_density_magnetization.restype = c_int
@@ -221,6 +223,14 @@ class System:
                                 (c_double * 3)(*q.pol))
         self._check(lib().nct_set_laser(self.h, len(pl), ctypes.cast(arr, POINTER(LaserPulse)) if pl else None))
 
+    def set_kpoints(self, kvec=None):
+        """Bloch vector [S, 3] of each state (None: Gamma only); k-weights go into occ."""
+        if kvec is None:
+            self._check(lib().nct_set_kpoints(self.h, None))
+            return
+        k = np.ascontiguousarray(np.asarray(kvec, dtype=np.float64).reshape(-1, 3))
+        self._check(lib().nct_set_kpoints(self.h, k.ctypes.data_as(c_void_p)))
+
     def density_magnetization(self, psi, t: float = 0.0, rho_v=None, totals: bool = False,
                               update_fields: bool = False):
         tot = np.zeros(4)
@@ -280,6 +290,8 @@ def system_from_workload(w, precision: int = NCT_FP64, tape_steps: int = 0, dt=N
     s.set_potentials(v_ext=v, B0=w.bfield.B0, pulses=w.bfield.pulses)
     if getattr(w, "laser", None):
         s.set_laser(w.laser)
+    if getattr(w, "kvec", None) is not None:
+        s.set_kpoints(w.kvec)
     torch.cuda.synchronize()
     return s
 
