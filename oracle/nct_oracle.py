@@ -323,8 +323,25 @@ class LaserPulseSpec:
 @dataclass
 class LaserSpec:
     """Uniform electric field E(t) = sum_k A_k pol_k cos(omega_k t + phase_k)
-    exp(-(t - t0_k)^2 / (2 tau_k^2))  (pulse profile of the optical runs, Sec. 4.7)."""
+    exp(-(t - t0_k)^2 / (2 tau_k^2))  (pulse profile of the optical runs, Sec. 4.7).
+
+    gauge "length": v_E = E(t).(r - c) (isolated systems);  gauge "velocity": the kinetic momentum
+    of every state is shifted by the vector potential A(t) = -int_0^t E dt' (periodic systems):
+    1/2 |G + k + A|^2 and projector phases exp(+/- i (k + A).d)."""
     pulses: List[LaserPulseSpec] = field(default_factory=list)
+    gauge: str = "length"
+
+    def A(self, t: float) -> np.ndarray:
+        """Vector potential -int_0^t E(t') dt' by adaptive quadrature (scipy.integrate.quad)."""
+        from scipy.integrate import quad
+        out = np.zeros(3)
+        if t == 0.0 or not self.pulses:
+            return out
+        for d in range(3):
+            f = lambda tt: float(self.E(tt)[d])
+            val, _ = quad(f, 0.0, t, epsabs=1e-14, epsrel=1e-12, limit=400)
+            out[d] = -val
+        return out
 
     def E(self, t: float) -> np.ndarray:
         out = np.zeros(3)
@@ -531,7 +548,8 @@ class Fields:
     n: np.ndarray
     m: np.ndarray
     B: np.ndarray
-    vE: np.ndarray = None  # laser potential at t (zeros without a laser)
+    vE: np.ndarray = None  # laser potential at t (zeros without a laser or in the velocity gauge)
+    A: np.ndarray = None   # velocity-gauge vector potential at t (None in the length gauge)
 
 
 def fields_from_density(sysd: System, rho_v: np.ndarray, t: float) -> Fields:
@@ -548,17 +566,31 @@ def fields_from_density(sysd: System, rho_v: np.ndarray, t: float) -> Fields:
     else:
         vbar, bxc, ex = np.zeros_like(n), np.zeros_like(m), np.zeros_like(n)
     B = sysd.bfield.B(t)
-    vE = laser_potential(grid, sysd.laser.E(t))
+    A = None
+    if sysd.laser.gauge == "velocity":
+        vE = np.zeros_like(n)
+        A = sysd.laser.A(t) if sysd.laser.pulses else None
+    else:
+        vE = laser_potential(grid, sysd.laser.E(t))
     v = sysd.v_ext + vE + vH + vbar
     b = bxc + MU_B * B[:, None, None, None]
-    return Fields(v, b, vH, vbar, bxc, ex, n, m, B, vE)
+    return Fields(v, b, vH, vbar, bxc, ex, n, m, B, vE, A)
+
+
+def effective_kvec(sysd: System, F: Fields, S: int) -> Optional[np.ndarray]:
+    """Bloch vectors of the states, shifted by the velocity-gauge vector potential if any."""
+    if F.A is None:
+        return sysd.kvec
+    base = np.zeros((S, 3)) if sysd.kvec is None else sysd.kvec
+    return base + F.A[None, :]
 
 
 def apply_hamiltonian(sysd: System, psi: np.ndarray, F: Fields) -> np.ndarray:
     """H psi = T psi + [v + b.sigma] psi + V_NL psi  (Eq. TDSDFT with the pseudopotential of Eq. Vps)."""
-    out = kinetic(psi, sysd.grid, sysd.kvec) + apply_local(psi, F.v, F.b)
+    kv = effective_kvec(sysd, F, psi.shape[0])
+    out = kinetic(psi, sysd.grid, kv) + apply_local(psi, F.v, F.b)
     if sysd.projs:
-        out = out + apply_nonlocal(psi, sysd.projs, sysd.grid, sysd.kvec)
+        out = out + apply_nonlocal(psi, sysd.projs, sysd.grid, kv)
     return out
 
 
@@ -613,12 +645,13 @@ def observables(sysd: System, psi: np.ndarray, t: float) -> np.ndarray:
     Ne = n.sum() * dV
     M = m.reshape(3, -1).sum(axis=1) * dV
     f = sysd.occ
-    Tpsi = kinetic(psi, grid, sysd.kvec)
+    kv = effective_kvec(sysd, F, psi.shape[0])
+    Tpsi = kinetic(psi, grid, kv)
     ekin = float(np.sum(f * np.real(np.sum(psi.conj() * Tpsi, axis=(1, 2, 3, 4)))) * dV)
     eloc = float(np.sum((sysd.v_ext + F.vE) * n) * dV)
     enl = 0.0
     if sysd.projs:
-        for ap, C in zip(sysd.projs, projections(psi, sysd.projs, grid, sysd.kvec)):
+        for ap, C in zip(sysd.projs, projections(psi, sysd.projs, grid, kv)):
             enl += float(np.sum(f[None, :] * ap.energy[:, None] * np.abs(C) ** 2))
     eh = float(0.5 * np.sum(F.vH * n) * dV)
     exc = float(np.sum(F.ex) * dV)
@@ -739,7 +772,7 @@ def system_from_workload(w, dt: Optional[float] = None) -> System:
                    [PulseSpec(p.A, p.omega, p.t0, p.tau, p.phase, tuple(p.e1), tuple(p.e2))
                     for p in w.bfield.pulses])
     laser = LaserSpec([LaserPulseSpec(p.A, p.omega, p.t0, p.tau, p.phase, tuple(p.pol))
-                       for p in getattr(w, "laser", [])])
+                       for p in getattr(w, "laser", [])], getattr(w, "laser_gauge", "length"))
     return System(grid=grid, occ=np.asarray(w.occ, dtype=np.float64), v_ext=w.v_ext,
                   projs=projs, bfield=bf, xc=w.xc, hartree=w.hartree, thr=w.m_threshold,
                   dt=w.dt if dt is None else dt, K=w.taylor_order, laser=laser,

@@ -112,6 +112,7 @@ class Workload:
     checkpoint_every: int = 0
     laser: List[LaserPulse] = dataclasses.field(default_factory=list)
     kvec: Optional[np.ndarray] = None   # [S, 3] Bloch vector of each state (None: Gamma only)
+    laser_gauge: str = "length"         # "length" (isolated) or "velocity" (periodic)
 
     @property
     def natoms(self) -> int:

@@ -752,6 +752,38 @@ def test_laser_rotates_magnetisation_only_through_soc(lam):
         assert perp > 1e-4
 
 
+def test_velocity_gauge_ehrenfest_and_free_phase():
+    """Velocity gauge: a packet at rest in a static field keeps its canonical momentum while its
+    kinetic momentum grows as A(t) = -E t, so <r> - c = -E t^2/2 exactly, periodic boundaries and
+    all; and a plane wave picks up exactly the Taylor factors of 1/2 |G + A(t)|^2 with A taken at
+    t_n for the first two half steps and t_{n+1} for the third."""
+    E0, T = 0.5, 1.2
+    sysd, psi, rel = _laser_packet_system(0.04, E0)
+    sysd.laser.gauge = "velocity"
+    assert np.allclose(sysd.laser.A(0.7), [0.0, 0.0, -E0 * 0.7], atol=1e-14)
+    p, obs = O.run(sysd, psi, 30)
+    n, _ = O.charge_and_magnetization(O.spin_density(p, sysd.occ))
+    disp = [float(np.sum(n * r) * sysd.grid.dV) for r in rel]
+    assert abs(disp[2] + 0.5 * E0 * T * T) < 1e-6
+    assert abs(obs[-1, 6] - obs[0, 6] - 0.5 * E0 * E0 * T * T) < 1e-5   # kinetic energy of the packet
+    grid = O.Grid((8, 8, 8), (5.0, 5.0, 5.0))
+    sysw = _free_system(grid.n, grid.L, dt=0.1)
+    sysw.laser = O.LaserSpec([O.LaserPulseSpec(A=0.3, omega=0.9, t0=0.2, tau=0.4, phase=0.1,
+                                               pol=(0.6, 0.0, 0.8))], "velocity")
+    G = np.array([2 * math.pi / 5.0, 0.0, -2 * math.pi / 5.0])
+    pw, _ = _plane_wave(grid, (1, 0, -1), np.array([1.0, 0.0]))
+    cur = pw
+    amp = 1.0 + 0j
+    for nstep in range(4):
+        t = 0.1 * nstep
+        e_n = 0.5 * float(np.sum((G + sysw.laser.A(t)) ** 2))
+        e_p = 0.5 * float(np.sum((G + sysw.laser.A(t + 0.1)) ** 2))
+        # phi = T(e_n) psi_n, psi_{n+1} = T(e_{n+1}) phi
+        amp *= _taylor_scalar(-1j * e_p * 0.05, 4) * _taylor_scalar(-1j * e_n * 0.05, 4)
+        cur = O.etrs_step(sysw, cur, t)
+        assert np.allclose(cur, amp * pw, atol=1e-13)
+
+
 # ---------------------------------------------------------------- gradient oracle
 def test_tangent_linear_gradient_matches_central_differences():
     bf = I.BField(pulses=I.circular_pulses([0.1, 0.2], [0.5, 1.0], 0.05, 0.1))
