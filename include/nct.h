@@ -155,6 +155,16 @@ typedef struct {
  * a non-finite parameter. */
 nct_status nct_set_laser(nct_system *sys, int npulses, const nct_laser_pulse *pulses);
 
+/* Gauge of the laser set by nct_set_laser.
+ *   NCT_GAUGE_LENGTH (default): v_E = E(t).(r - c) as described there (isolated systems);
+ *   NCT_GAUGE_VELOCITY: for periodic systems; every state's kinetic momentum is shifted by the
+ *     vector potential A(t) = -int_0^t E dt' (evaluated like B_ext: t_n for H_n, t_n + dt for
+ *     H~): kinetic factor 1/2 |G + k + A|^2 and projector phases exp(+/- i (k + A).d), no scalar
+ *     potential and no E.D term in E_loc.  nct_backward_step refuses it (NCT_ERR_UNSUPPORTED).
+ * Errors: NCT_ERR_ARG for any other value. */
+enum { NCT_GAUGE_LENGTH = 0, NCT_GAUGE_VELOCITY = 1 };
+nct_status nct_set_laser_gauge(nct_system *sys, int gauge);
+
 /* k-point sampling (the state index i = (n, k) of Eq. KSDFT; Sec. 5 runs 8 k-points of a bcc
  * supercell).  kvec host double [nstates][3]: the Bloch vector of each state (bohr^-1, copied);
  * the states then hold the periodic parts u_i of psi_i = exp(i k_i.r) u_i: the kinetic factor

@@ -65,7 +65,10 @@ struct nct_system {
   std::vector<double> positions_h;
   std::vector<nct_channel> channels_h;
   std::vector<nct_pulse> pulses;
-  std::vector<nct_laser_pulse> laser;   // uniform electric pulses (length gauge)
+  std::vector<nct_laser_pulse> laser;   // uniform electric pulses
+  int laser_gauge = NCT_GAUGE_LENGTH;
+  double* kv_zero64 = nullptr;          // [S][3] zeros: Bloch vectors for the velocity gauge at Gamma
+  float* kv_zero32 = nullptr;
   double B0[3] = {0, 0, 0};
   bool frozen = false;
   bool fields_valid = false;
@@ -339,10 +342,20 @@ void gauss_legendre(int n, std::vector<double>& xs, std::vector<double>& ws) {
   }
 }
 
+// 24-point Gauss-Legendre rule on [-1, 1], built once (thread-safe static initialisation)
+struct GLRule {
+  std::vector<double> x, w;
+  explicit GLRule(int n) { gauss_legendre(n, x, w); }
+};
+const GLRule& gl24() {
+  static const GLRule rule(24);
+  return rule;
+}
+
 // sqrt( int_0^rs (r^l e^{-r^2/2rc^2})^2 r^2 dr ), composite Gauss-Legendre
 double radial_norm(int l, double rc, double rs) {
-  static std::vector<double> xs, ws;
-  if (xs.empty()) gauss_legendre(24, xs, ws);
+  const std::vector<double>& xs = gl24().x;
+  const std::vector<double>& ws = gl24().w;
   const int panels = 16;
   double acc = 0.0;
   for (int p = 0; p < panels; ++p) {
@@ -518,6 +531,33 @@ void efield_at(const nct_system* s, double t, double E[3]) {
   }
 }
 
+// Velocity-gauge vector potential A(t) = -int_0^t E dt' (composite 24-point Gauss-Legendre on
+// panels no wider than a quarter of the shortest pulse width or period).
+bool velocity_gauge(const nct_system* s) {
+  return s->laser_gauge == NCT_GAUGE_VELOCITY && !s->laser.empty() && !s->frozen;
+}
+void vector_potential_at(const nct_system* s, double t, double A[3]) {
+  A[0] = A[1] = A[2] = 0.0;
+  if (s->laser.empty() || t == 0.0) return;
+  const std::vector<double>& xs = gl24().x;
+  const std::vector<double>& ws = gl24().w;
+  double hmax = 1e300;
+  for (const nct_laser_pulse& p : s->laser) {
+    hmax = std::min(hmax, 0.25 * p.tau);
+    if (p.omega != 0.0) hmax = std::min(hmax, 0.25 * 2.0 * kPi / std::fabs(p.omega));
+  }
+  const int panels = std::max(1, int(std::ceil(std::fabs(t) / hmax)));
+  const double h = t / panels;
+  for (int q = 0; q < panels; ++q) {
+    const double a = q * h;
+    for (size_t i = 0; i < xs.size(); ++i) {
+      double E[3];
+      efield_at(s, a + 0.5 * h * (xs[i] + 1.0), E);
+      for (int d = 0; d < 3; ++d) A[d] -= 0.5 * h * ws[i] * E[d];
+    }
+  }
+}
+
 // Length-gauge potential v_E = E.(r - c) at grid point (ix, iy, iz) as lg[0] ix + lg[1] iy +
 // lg[2] iz + lg[3]: lg[d] = E_d h_d, lg[3] = -E.c with c the cell centre.
 void laser_coeffs(const nct_system* s, double t, double lg[4]) {
@@ -557,8 +597,9 @@ struct Engine {
   const R* g2x() const { return sizeof(R) == 8 ? (const R*)s->g2x64 : (const R*)s->g2x32; }
   const R* g2yz() const { return sizeof(R) == 8 ? (const R*)s->g2yz64 : (const R*)s->g2yz32; }
   const R* kvR() const {
-    if (!s->has_k) return nullptr;
-    return sizeof(R) == 8 ? (const R*)s->kv64 : (const R*)s->kv32;
+    if (s->has_k) return sizeof(R) == 8 ? (const R*)s->kv64 : (const R*)s->kv32;
+    if (velocity_gauge(s)) return sizeof(R) == 8 ? (const R*)s->kv_zero64 : (const R*)s->kv_zero32;
+    return nullptr;
   }
   KTables<R> ktab(int state_off = 0) const {
     KTables<R> k;
@@ -567,6 +608,7 @@ struct Engine {
     k.gz = sizeof(R) == 8 ? (const R*)s->gsz64 : (const R*)s->gsz32;
     k.kv = kvR();
     k.state_off = state_off;
+    for (int d = 0; d < 3; ++d) k.ka[d] = R(ka[d]);
     return k;
   }
   const R* fieldsR() const { return sizeof(R) == 8 ? (const R*)s->fields : (const R*)s->fields32; }
@@ -649,12 +691,22 @@ struct Engine {
     return NCT_OK;
   }
 
-  // external fields of a plane-pass stage at time t: mu_B B_ext(t) and the laser potential
+  // velocity-gauge vector potential of the H being applied (zero otherwise)
+  double ka[3] = {0, 0, 0};
+  void at_time(double t) {
+    if (velocity_gauge(s)) vector_potential_at(s, t, ka);
+    else ka[0] = ka[1] = ka[2] = 0.0;
+  }
+
+  // external fields of a plane-pass stage at time t: mu_B B_ext(t) and the laser (length-gauge
+  // potential, or the velocity-gauge shift of the Bloch vectors)
   void externals(double t, StageArgs<R>& sa) {
     bext_now(t, sa.bext);
+    at_time(t);
     double lg[4] = {0, 0, 0, 0};
-    if (!s->frozen && !s->laser.empty()) laser_coeffs(s, t, lg);
+    if (!s->frozen && !s->laser.empty() && !velocity_gauge(s)) laser_coeffs(s, t, lg);
     for (int k = 0; k < 4; ++k) sa.lg[k] = R(lg[k]);
+    for (int k = 0; k < 3; ++k) sa.ka[k] = R(ka[k]);
   }
 
   void bext_now(double t, R out[3]) {
@@ -833,12 +885,13 @@ struct Engine {
   nct_status prepare(const void* psi, void* hat, void* W) {
     return check(timed(s, NCT_K_PLANE_FWD, 2 * psiB() + (s->natoms ? rowsB() : 0.0), 0, [&] {
                    return launch_plane_fwd<R>(s->n, 2 * s->S, psi, hat, s->natoms ? W : nullptr, &s->pt,
-                                              twy(), twz(), s->st, kvR()); }), "plane_fwd");
+                                              twy(), twz(), s->st, ktab()); }), "plane_fwd");
   }
 
   nct_status obs_row(double t, double* row) {
     nct_status r;
     int ntiles = 0;
+    at_time(t);
     if ((r = check(timed(s, NCT_K_OBS, psiB(), 0, [&] {
            return launch_xpass_energy<R>(s->n, 2 * s->S, s->psihat, g2x(), g2yz(), R(0.5 / double(s->N)),
                                          twx(), s->epart, &ntiles, s->st, ktab()); }), "energy")) != NCT_OK)
@@ -863,7 +916,7 @@ struct Engine {
     double B[3] = {0, 0, 0}, E[3] = {0, 0, 0};
     if (!s->frozen) {
       bfield_at(s, t, B);
-      efield_at(s, t, E);
+      if (!velocity_gauge(s)) efield_at(s, t, E);
     }
     for (int k = 0; k < 3; ++k) {
       in.muB_B[k] = kMuB * B[k];
@@ -903,6 +956,7 @@ struct Engine {
       T->valid = 0;
       T->t0 = t0;
     }
+    at_time(t0);
     if ((r = prepare(cur, s->psihat, s->Wpsi)) != NCT_OK) return r;
     if (!s->frozen) {
       if ((r = density(cur)) != NCT_OK) return r;
@@ -933,16 +987,27 @@ struct Engine {
       }
       if ((r = taylor(cur, s->psihat, s->Wpsi, phi, s->phihat, s->Wphi, t, T ? so1.data() : nullptr)) != NCT_OK)
         return r;
+      // the second and third exponentials share phi's kinetic column pass unless the kinetic
+      // term itself depends on time (velocity-gauge laser)
+      const bool vg = velocity_gauge(s);
       if ((r = taylor(phi, s->phihat, s->Wphi, ptil, nullptr, nullptr, t, T ? so2.data() : nullptr,
-                      s->tmpk_phi)) != NCT_OK)
+                      vg ? nullptr : s->tmpk_phi)) != NCT_OK)
         return r;
       if (!s->frozen) {
         if ((r = density(ptil)) != NCT_OK) return r;
         if ((r = fields_from_rho(true)) != NCT_OK) return r;
       }
       if (T && (r = save_fields(*T, k, 1)) != NCT_OK) return r;
+      if (vg && s->natoms) {  // phi's rows were gathered under A(t): carry them to A(t + dt)
+        double a0[3], a1[3], dA[3];
+        vector_potential_at(s, t, a0);
+        vector_potential_at(s, t + dt, a1);
+        for (int d = 0; d < 3; ++d) dA[d] = a1[d] - a0[d];
+        if ((r = check(launch_rephase_rows<R>(s->pt, s->Wphi, s->S, dA, s->st), "rephase")) != NCT_OK)
+          return r;
+      }
       if ((r = taylor(phi, s->phihat, s->Wphi, next, s->psihat, s->Wpsi, t + dt, T ? so3.data() : nullptr,
-                      nullptr, s->tmpk_phi)) != NCT_OK)
+                      nullptr, vg ? nullptr : s->tmpk_phi)) != NCT_OK)
         return r;
       cur = next;
       if (!s->frozen || obs_host) {
@@ -1118,6 +1183,7 @@ struct Engine {
 
   nct_status apply(const void* psi, void* hpsi, double t) {
     nct_status r;
+    at_time(t);
     if ((r = prepare(psi, s->tmp, s->Wwork)) != NCT_OK) return r;
     if ((r = projections(s->Wwork)) != NCT_OK) return r;
     if ((r = xpass(s->tmp, s->tmp)) != NCT_OK) return r;
@@ -1413,6 +1479,26 @@ const char* nct_last_error(const nct_system* sys) {
   return sys ? sys->err.c_str() : g_create_error.c_str();
 }
 
+nct_status nct_set_laser_gauge(nct_system* s, int gauge) {
+  if (!s) return NCT_ERR_ARG;
+  if (gauge != NCT_GAUGE_LENGTH && gauge != NCT_GAUGE_VELOCITY)
+    return fail(s, NCT_ERR_ARG, "gauge must be NCT_GAUGE_LENGTH or NCT_GAUGE_VELOCITY");
+  if (gauge == NCT_GAUGE_VELOCITY && !s->kv_zero64) {
+    const size_t n = size_t(s->S) * 3;
+    void* p;
+    nct_status r;
+    if ((r = dalloc(s, n * sizeof(double), &p)) != NCT_OK) return r;
+    s->kv_zero64 = static_cast<double*>(p);
+    if ((r = dalloc(s, n * sizeof(float), &p)) != NCT_OK) return r;
+    s->kv_zero32 = static_cast<float*>(p);
+    HIPCHK(s, hipMemsetAsync(s->kv_zero64, 0, n * sizeof(double), s->st));
+    HIPCHK(s, hipMemsetAsync(s->kv_zero32, 0, n * sizeof(float), s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+  }
+  s->laser_gauge = gauge;
+  return NCT_OK;
+}
+
 nct_status nct_set_kpoints(nct_system* s, const double* kvec) {
   if (!s) return NCT_ERR_ARG;
   if (!kvec) {
@@ -1513,7 +1599,7 @@ nct_status nct_get_fields(nct_system* s, double t, double* out) {
   if (!s->frozen) {
     bfield_at(s, t, B);
     for (int k = 0; k < 3; ++k) B[k] *= kMuB;
-    if (!s->laser.empty()) laser_coeffs(s, t, lg);
+    if (!s->laser.empty() && !velocity_gauge(s)) laser_coeffs(s, t, lg);
   }
   HIPCHK(s, launch_add_bext(s->fields, s->n, B, lg, out, s->st));
   return NCT_OK;
@@ -1555,6 +1641,8 @@ nct_status nct_backward_step(nct_system* s, int tape_index, const void* psi_n, d
   if (s->frozen && !s->fields_valid) return fail(s, NCT_ERR_STATE, "no fields");
   if (s->prm.xc >= 2 && !s->frozen)
     return fail(s, NCT_ERR_UNSUPPORTED, "the adjoint step covers exchange only (xc <= 1)");
+  if (velocity_gauge(s))
+    return fail(s, NCT_ERR_UNSUPPORTED, "the adjoint step does not cover the velocity-gauge laser");
   nct_system::Tape* T = nullptr;
   int idx = 0;
   nct_status r;

@@ -48,9 +48,11 @@ struct StageArgs {
   void* acc = nullptr;
   // cache policy of the state-sized operands: 0 plain, 1 streaming stores, 2 streaming loads too
   int cache_mode = 0;
-  // Bloch vectors [S][3] of the states (null: Gamma only); this launch's state 0 is state_off
+  // Bloch vectors [S][3] of the states (null: Gamma only); this launch's state 0 is state_off;
+  // ka: velocity-gauge vector potential added to every Bloch vector
   const R* kv = nullptr;
   int state_off = 0;
+  R ka[3] = {0, 0, 0};
 };
 
 // Kinetic factor with Bloch vectors: |G + k|^2 from signed per-axis G tables (gx in the
@@ -63,6 +65,7 @@ struct KTables {
   const R* gz = nullptr;
   const R* kv = nullptr;   // [S][3]
   int state_off = 0;       // state of batch entries 0, 1
+  R ka[3] = {0, 0, 0};     // velocity-gauge vector potential added to every Bloch vector
 };
 
 // Launchers (return hipError_t of the launch).  n = {NX, NY, NZ}.
@@ -71,11 +74,17 @@ hipError_t launch_plane_stage(const int n[3], int S, const StageArgs<R>& a, cons
                               const void* twy, const void* twz, hipStream_t st);
 // Forward 2D transform of B planes-sets (batch entries, each [NX][NY][NZ]); optionally gathers
 // sphere rows of the input into W (batch must then be 2S in state/spinor order).
-// With kv (Bloch vectors [S][3]) the gathered rows carry exp(i k.d) (state of entry b = b / 2).
+// With kt.kv (Bloch vectors [S][3], shifted by kt.ka) the gathered rows carry exp(i k.d) (state
+// of entry b = b / 2).
 template <typename R>
 hipError_t launch_plane_fwd(const int n[3], int B, const void* in, void* out, void* W,
                             const ProjTables* pt, const void* twy, const void* twz, hipStream_t st,
-                            const R* kv = nullptr);
+                            KTables<R> kt = KTables<R>{});
+// rows[S][2][Jtot] *= exp(i dA.d_J): sphere rows gathered under one vector potential carried to
+// another (dA = A_new - A_old).
+template <typename R>
+hipError_t launch_rephase_rows(const ProjTables& pt, void* rows, int S, const double dA[3],
+                               hipStream_t st);
 // Inverse 2D transform; out = scale * result.
 template <typename R>
 hipError_t launch_plane_inv(const int n[3], int B, const void* in, void* out, R scale,

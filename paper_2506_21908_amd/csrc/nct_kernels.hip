@@ -192,7 +192,15 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a
     }
     __syncthreads();
     const size_t rowbase = size_t(2 * i + s) * pt.Jtot;
-    const R* kq = a.kv ? a.kv + 3 * (a.state_off + i) : nullptr;
+    R qv[3] = {0, 0, 0};
+    const R* kq = nullptr;
+    if (a.kv) {
+      const R* k0 = a.kv + 3 * (a.state_off + i);
+      qv[0] = k0[0] + a.ka[0];
+      qv[1] = k0[1] + a.ka[1];
+      qv[2] = k0[2] + a.ka[2];
+      kq = qv;
+    }
     const R* disp = reinterpret_cast<const R*>(pt.disp);
     if (Y) {
       for (int r = r0; r < r1; ++r) {
@@ -392,7 +400,15 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(Stag
   const int r0 = pt.pr_off ? pt.pr_off[x] : 0;
   const int r1 = pt.pr_off ? pt.pr_off[x + 1] : 0;
   const size_t rowbase = size_t(2 * i + h) * pt.Jtot;
-  const R* kq = a.kv ? a.kv + 3 * (a.state_off + i) : nullptr;
+  R qv[3] = {0, 0, 0};
+  const R* kq = nullptr;
+  if (a.kv) {
+    const R* k0 = a.kv + 3 * (a.state_off + i);
+    qv[0] = k0[0] + a.ka[0];
+    qv[1] = k0[1] + a.ka[1];
+    qv[2] = k0[2] + a.ka[2];
+    kq = qv;
+  }
   const R* disp = reinterpret_cast<const R*>(pt.disp);
   if (Y) {
     for (int r = r0; r < r1; ++r) {
@@ -453,8 +469,7 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_fwd(const cpx<R>* in
                                                                  cpx<R>* W, ProjTables pt,
                                                                  const cpx<R>* __restrict__ twy_g,
                                                                  const cpx<R>* __restrict__ twz_g,
-                                                                 int B, int NX,
-                                                                 const R* __restrict__ kv) {
+                                                                 int B, int NX, KTables<R> kt) {
   constexpr int NP = NY * NZ;
   constexpr int NT = plane_nt(NP);
   constexpr int PZ = NZ + 1;
@@ -473,7 +488,15 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_fwd(const cpx<R>* in
   __syncthreads();
   if (W && pt.pr_off) {
     const size_t rowbase = size_t(b) * pt.Jtot;
-    const R* kq = kv ? kv + 3 * (b / 2) : nullptr;
+    R qv[3] = {0, 0, 0};
+    const R* kq = nullptr;
+    if (kt.kv) {
+      const R* k0 = kt.kv + 3 * (kt.state_off + b / 2);
+      qv[0] = k0[0] + kt.ka[0];
+      qv[1] = k0[1] + kt.ka[1];
+      qv[2] = k0[2] + kt.ka[2];
+      kq = qv;
+    }
     const R* disp = reinterpret_cast<const R*>(pt.disp);
     for (int r = pt.pr_off[x]; r < pt.pr_off[x + 1]; ++r) {
       for (int J = pt.pr_begin[r] + tid; J < pt.pr_end[r]; J += NT) {
@@ -578,9 +601,9 @@ _Pragma("clang loop unroll(full)")
         R g;
         if (kt.kv) {  // |G + k|^2 of this spinor component's state
           const R* k = kt.kv + 3 * (kt.state_off + b / 2);
-          const R gx = kt.gx[e / TC] + k[0];
-          const R gy = kt.gy[q0 + (e % TC)] + k[1];
-          const R gz = kt.gz[q0 + (e % TC)] + k[2];
+          const R gx = kt.gx[e / TC] + (k[0] + kt.ka[0]);
+          const R gy = kt.gy[q0 + (e % TC)] + (k[1] + kt.ka[1]);
+          const R gz = kt.gz[q0 + (e % TC)] + (k[2] + kt.ka[2]);
           g = gx * gx + gy * gy + gz * gz;
         } else {
           g = g2x[e / TC] + g2yz[q0 + (e % TC)];
@@ -640,9 +663,9 @@ __global__ __launch_bounds__(XP_NT) void k_xpass_energy(const cpx<R>* src, int N
     double g;
     if (kt.kv) {
       const R* k = kt.kv + 3 * (kt.state_off + b / 2);
-      const double gx = double(kt.gx[xx]) + double(k[0]);
-      const double gy = double(kt.gy[q0 + c]) + double(k[1]);
-      const double gz = double(kt.gz[q0 + c]) + double(k[2]);
+      const double gx = double(kt.gx[xx]) + double(k[0] + kt.ka[0]);
+      const double gy = double(kt.gy[q0 + c]) + double(k[1] + kt.ka[1]);
+      const double gz = double(kt.gz[q0 + c]) + double(k[2] + kt.ka[2]);
       g = gx * gx + gy * gy + gz * gz;
     } else {
       g = double(g2x[xx]) + double(g2yz[q0 + c]);
@@ -1242,6 +1265,17 @@ __global__ void k_axpby(cpx<R>* __restrict__ y, const cpx<R>* __restrict__ x, si
   y[idx] = {are * xv.x - aim * xv.y + b * yv.x, are * xv.y + aim * xv.x + b * yv.y};
 }
 
+// rows[S][2][Jtot] *= exp(i dA.d_J)
+template <typename R>
+__global__ __launch_bounds__(256) void k_rephase_rows(cpx<R>* __restrict__ rows, const R* __restrict__ disp,
+                                                      int Jtot, size_t total, R a0, R a1, R a2) {
+  const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p >= total) return;
+  const int J = int(p % size_t(Jtot));
+  const R q[3] = {a0, a1, a2};
+  rows[p] = cmul(rows[p], bloch_phase(q, disp + 3 * J));
+}
+
 // ================================================================ launchers
 static inline unsigned nblocks(size_t n, unsigned bs) { return unsigned((n + bs - 1) / bs); }
 
@@ -1327,7 +1361,7 @@ hipError_t launch_plane_stage(const int n[3], int S, const StageArgs<R>& a, cons
 template <typename R>
 hipError_t launch_plane_fwd(const int n[3], int B, const void* in, void* out, void* W,
                             const ProjTables* pt, const void* twy, const void* twz, hipStream_t st,
-                            const R* kv) {
+                            KTables<R> kt) {
   const unsigned grid = unsigned(B) * unsigned(n[0]);
   ProjTables none;
   const ProjTables& p = pt ? *pt : none;
@@ -1341,12 +1375,23 @@ hipError_t launch_plane_fwd(const int n[3], int B, const void* in, void* out, vo
                        reinterpret_cast<const cpx<R>*>(in), reinterpret_cast<cpx<R>*>(out),  \
                        reinterpret_cast<cpx<R>*>(W), p,                                     \
                        reinterpret_cast<const cpx<R>*>(twy), reinterpret_cast<const cpx<R>*>(twz), \
-                       B, n[0], kv);                                                        \
+                       B, n[0], kt);                                                        \
     return hipGetLastError();                                                               \
   }
   NCT_PLANE_PAIRS(X)
 #undef X
   return hipErrorInvalidValue;
+}
+
+template <typename R>
+hipError_t launch_rephase_rows(const ProjTables& pt, void* rows, int S, const double dA[3],
+                               hipStream_t st) {
+  if (pt.natoms == 0 || pt.Jtot == 0) return hipSuccess;
+  const size_t total = size_t(S) * 2 * pt.Jtot;
+  nct_launch(k_rephase_rows<R>, dim3(nblocks(total, 256)), dim3(256), 0, st,
+             reinterpret_cast<cpx<R>*>(rows), reinterpret_cast<const R*>(pt.disp), pt.Jtot, total,
+             R(dA[0]), R(dA[1]), R(dA[2]));
+  return hipGetLastError();
 }
 
 template <typename R>
@@ -1574,7 +1619,9 @@ hipError_t launch_real_to_cpx(const double* r, size_t N, void* out, hipStream_t 
                                             const void*, const void*, hipStream_t);                \
   template hipError_t launch_plane_fwd<R>(const int*, int, const void*, void*, void*,              \
                                           const ProjTables*, const void*, const void*, hipStream_t, \
-                                          const R*);                                               \
+                                          KTables<R>);                                             \
+  template hipError_t launch_rephase_rows<R>(const ProjTables&, void*, int, const double*,       \
+                                             hipStream_t);                                         \
   template hipError_t launch_plane_inv<R>(const int*, int, const void*, void*, R, const void*,     \
                                           const void*, hipStream_t);                               \
   template hipError_t launch_xpass<R>(const int*, int, const void*, void*, const R*, const R*, R,  \

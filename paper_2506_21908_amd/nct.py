@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnct.so")
 
 NCT_OK, NCT_ERR_ARG, NCT_ERR_UNSUPPORTED, NCT_ERR_OOM, NCT_ERR_HIP, NCT_ERR_NONFINITE, NCT_ERR_STATE = range(7)
+NCT_GAUGE_LENGTH, NCT_GAUGE_VELOCITY = 0, 1
 NCT_FP64, NCT_FP32_MIXED = 0, 1
 STATUS_NAMES = {0: "NCT_OK", 1: "NCT_ERR_ARG", 2: "NCT_ERR_UNSUPPORTED", 3: "NCT_ERR_OOM",
                 4: "NCT_ERR_HIP", 5: "NCT_ERR_NONFINITE", 6: "NCT_ERR_STATE"}
@@ -80,6 +81,8 @@ def lib():
         L.nct_set_laser.restype = c_int
         L.nct_set_kpoints.argtypes = [c_void_p, c_void_p]
         L.nct_set_kpoints.restype = c_int
+        L.nct_set_laser_gauge.argtypes = [c_void_p, c_int]
+        L.nct_set_laser_gauge.restype = c_int
         L.nct_density_magnetization.argtypes = [c_void_p, c_void_p, c_double, c_void_p,
                                                 POINTER(c_double), c_int]
         L.nct_density_magnetization.restype = c_int
@@ -223,6 +226,11 @@ class System:
                                 (c_double * 3)(*q.pol))
         self._check(lib().nct_set_laser(self.h, len(pl), ctypes.cast(arr, POINTER(LaserPulse)) if pl else None))
 
+    def set_laser_gauge(self, gauge: str):
+        """"length" (isolated systems) or "velocity" (periodic systems)."""
+        code = {"length": NCT_GAUGE_LENGTH, "velocity": NCT_GAUGE_VELOCITY}.get(gauge, -1)
+        self._check(lib().nct_set_laser_gauge(self.h, code))
+
     def set_kpoints(self, kvec=None):
         """Bloch vector [S, 3] of each state (None: Gamma only); k-weights go into occ."""
         if kvec is None:
@@ -290,6 +298,7 @@ def system_from_workload(w, precision: int = NCT_FP64, tape_steps: int = 0, dt=N
     s.set_potentials(v_ext=v, B0=w.bfield.B0, pulses=w.bfield.pulses)
     if getattr(w, "laser", None):
         s.set_laser(w.laser)
+        s.set_laser_gauge(getattr(w, "laser_gauge", "length"))
     if getattr(w, "kvec", None) is not None:
         s.set_kpoints(w.kvec)
     torch.cuda.synchronize()

@@ -163,3 +163,55 @@ def test_laser_argument_errors(torch_cuda):
         s.set_laser(bad)
     assert e.value.code == nct.NCT_ERR_ARG
     s.set_laser([])   # removing is always allowed
+
+
+# ------------------------------------------------------------------ velocity gauge (periodic)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_velocity_gauge_step_vs_oracle(torch_cuda, prec):
+    """Velocity gauge with two k-points, SOC projectors and two pulses: the Bloch vectors shift by
+    A(t) in the kinetic pass and the projector phases, phi's rows are carried from A(t_n) to
+    A(t_{n+1}) before the third exponential; 8 steps against the oracle."""
+    from paper_2506_21908_amd import nct
+    say(f"velocity gauge {prec}")
+    w = I.make_system(n=(16, 12, 16), L=(8.0, 6.0, 8.0), nstates=4, natoms=2, case=53,
+                      laser=LASER, full_spinors=True, min_sep=3.0)
+    w.laser_gauge = "velocity"
+    w.kvec = np.repeat(np.array([[0.0, 0.0, 0.0], [0.2, -0.3, 0.1]]), 2, axis=0)
+    w.occ = np.full(4, 0.5)
+    sysd = O.system_from_workload(w)
+    psi_ref, obs_ref = O.run(sysd, w.psi0, 8)
+    pf = nct.NCT_FP64 if prec == "fp64" else nct.NCT_FP32_MIXED
+    s = nct.system_from_workload(w, precision=pf)
+    psi = nct.states_to_device(w.psi0, pf)
+    obs = s.step(psi, 0.0, 8, obs=True)
+    e_N, e_M, e_E = _traj_errors(obs, obs_ref[1:])
+    en, em = _nm_errors(psi.cpu().numpy().astype(np.complex128), psi_ref, sysd.occ)
+    say(f"  N_e {e_N:.2e} M {e_M:.2e} E {e_E:.2e} n {en:.2e} m {em:.2e}")
+    assert max(e_N, e_M, e_E, en, em) < (1e-10 if prec == "fp64" else 1e-5)
+    if prec == "fp64":
+        assert rel(psi.cpu().numpy(), psi_ref) < 1e-10
+
+
+def test_velocity_gauge_gamma_and_refusals(torch_cuda):
+    """Gamma-only system in the velocity gauge (the library supplies zero Bloch vectors) against the
+    oracle, the adjoint's refusal, and the gauge argument check."""
+    torch = torch_cuda
+    from paper_2506_21908_amd import nct
+    say("velocity gauge at Gamma")
+    w = I.make_system(n=(12, 12, 12), L=(7.0,) * 3, nstates=3, natoms=1, case=54, laser=LASER,
+                      full_spinors=True)
+    w.laser_gauge = "velocity"
+    sysd = O.system_from_workload(w)
+    psi_ref, obs_ref = O.run(sysd, w.psi0, 5)
+    s = nct.system_from_workload(w, tape_steps=1)
+    psi = nct.states_to_device(w.psi0)
+    obs = s.step(psi, 0.0, 5, obs=True)
+    assert max(_traj_errors(obs, obs_ref[1:])) < 1e-10
+    assert rel(psi.cpu().numpy(), psi_ref) < 1e-10
+    lam = torch.zeros_like(psi)
+    with pytest.raises(nct.NctError) as e:
+        s.backward_step(-1, psi, 0.0, lam, lam)
+    assert e.value.code == nct.NCT_ERR_UNSUPPORTED
+    with pytest.raises(nct.NctError) as e:
+        s.set_laser_gauge("coulomb")
+    assert e.value.code == nct.NCT_ERR_ARG
