@@ -247,13 +247,18 @@ enum {
 };
 
 /* Profiling aid.  nct_set_timing(sys, mask) resets the counters and, for every kernel class k
- * with bit k of mask set, records a pair of HIP events around each launch of that class (on the
- * system's stream); mask = 0 stops, mask = -1 records every class.
+ * with bit k of mask set, records a pair of HIP events on each launch of that class (attached to
+ * the dispatch, on the stream it runs on); mask = 0 stops, mask = -1 records every class.
  * nct_get_timing synchronises the stream and returns for kernel class kclass the summed
  * duration in milliseconds, the number of launches, and the algorithmic bytes and flops of
  * those launches (compulsory HBM traffic and useful arithmetic of the launch's definition,
  * not counters).  Outputs may be NULL. */
 nct_status nct_set_timing(nct_system *sys, int enable);
+/* Record only one launch in every 'every' launches of each enabled class (default 1: all).  The
+ * events ride on the kernel dispatch, which costs the stream ~10 us per recorded launch; sampling
+ * with a stride coprime to the launches per step still visits every stage of the step.
+ * Errors: NCT_ERR_ARG if every < 1. */
+nct_status nct_set_timing_sample(nct_system *sys, int every);
 nct_status nct_get_timing(nct_system *sys, int kclass, double *ms, long long *launches,
                           double *bytes, double *flops);
 

@@ -151,6 +151,8 @@ struct nct_system {
   };
   bool timing = false;
   unsigned timing_mask = 0;  // bit k: record class k (1: only the plane pass; all ones: everything)
+  int timing_every = 1;      // record one launch in this many of each class
+  long long t_seen[NCT_K_COUNT] = {0};
   std::vector<TimedLaunch> pending;
   std::vector<hipEvent_t> free_events;
   double t_ms[NCT_K_COUNT] = {0};
@@ -219,6 +221,7 @@ hipEvent_t take_event(nct_system* s) {
 template <typename F>
 hipError_t timed_on(nct_system* s, hipStream_t st, int k, double bytes, double flops, F&& launch) {
   if (!s->timing || !((s->timing_mask >> k) & 1u)) return launch();
+  if (s->t_seen[k]++ % s->timing_every != 0) return launch();
   hipEvent_t a = take_event(s), b = take_event(s);
   if (!a || !b) return launch();
   (void)st;  // the events ride on the dispatches themselves, on the stream they are launched on
@@ -1702,9 +1705,18 @@ nct_status nct_set_timing(nct_system* s, int enable) {
     s->t_count[k] = 0;
     s->t_bytes[k] = 0;
     s->t_flops[k] = 0;
+    s->t_seen[k] = 0;
   }
   s->timing_mask = unsigned(enable);
   s->timing = enable != 0;
+  return NCT_OK;
+}
+
+nct_status nct_set_timing_sample(nct_system* s, int every) {
+  if (!s) return NCT_ERR_ARG;
+  if (every < 1) return fail(s, NCT_ERR_ARG, "every must be >= 1");
+  s->timing_every = every;
+  for (int k = 0; k < NCT_K_COUNT; ++k) s->t_seen[k] = 0;
   return NCT_OK;
 }
 

@@ -82,14 +82,15 @@ __device__ __forceinline__ void st_stream(cpx<R>* p, cpx<R> v) {
 
 // Bloch phase exp(i q.d) of one sphere row (q: Bloch vector, d: the row's displacement from its
 // atom).  Rows gathered for the projections carry it, scattered rows its conjugate.
-__device__ __forceinline__ cpx<double> bloch_phase(const double* q, const double* d) {
+// (q passed as scalars: an addressable local array would live in scratch memory)
+__device__ __forceinline__ cpx<double> bloch_phase(double q0, double q1, double q2, const double* d) {
   double sn, cs;
-  sincos(q[0] * d[0] + q[1] * d[1] + q[2] * d[2], &sn, &cs);
+  sincos(q0 * d[0] + q1 * d[1] + q2 * d[2], &sn, &cs);
   return {cs, sn};
 }
-__device__ __forceinline__ cpx<float> bloch_phase(const float* q, const float* d) {
+__device__ __forceinline__ cpx<float> bloch_phase(float q0, float q1, float q2, const float* d) {
   float sn, cs;
-  sincosf(q[0] * d[0] + q[1] * d[1] + q[2] * d[2], &sn, &cs);
+  sincosf(q0 * d[0] + q1 * d[1] + q2 * d[2], &sn, &cs);
   return {cs, sn};
 }
 
@@ -192,14 +193,13 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a
     }
     __syncthreads();
     const size_t rowbase = size_t(2 * i + s) * pt.Jtot;
-    R qv[3] = {0, 0, 0};
-    const R* kq = nullptr;
-    if (a.kv) {
+    const bool kq = a.kv != nullptr;
+    R q0 = 0, q1 = 0, q2 = 0;
+    if (kq) {
       const R* k0 = a.kv + 3 * (a.state_off + i);
-      qv[0] = k0[0] + a.ka[0];
-      qv[1] = k0[1] + a.ka[1];
-      qv[2] = k0[2] + a.ka[2];
-      kq = qv;
+      q0 = k0[0] + a.ka[0];
+      q1 = k0[1] + a.ka[1];
+      q2 = k0[2] + a.ka[2];
     }
     const R* disp = reinterpret_cast<const R*>(pt.disp);
     if (Y) {
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a
         for (int J = jb + tid; J < je; J += NT) {
           const int e = pt.pidx[J];
           cpx<R> y = Y[rowbase + J];
-          if (kq) y = cmulc(y, bloch_phase(kq, disp + 3 * J));
+          if (kq) y = cmulc(y, bloch_phase(q0, q1, q2, disp + 3 * J));
           cpx<R>& d = plane[(e / NZ) * PZ + (e % NZ)];
           d.x += a.cre * y.x - a.cim * y.y;
           d.y += a.cre * y.y + a.cim * y.x;
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a
         for (int J = jb + tid; J < je; J += NT) {
           const int e = pt.pidx[J];
           cpx<R> o = plane[(e / NZ) * PZ + (e % NZ)];
-          if (kq) o = cmul(o, bloch_phase(kq, disp + 3 * J));
+          if (kq) o = cmul(o, bloch_phase(q0, q1, q2, disp + 3 * J));
           Wr[rowbase + J] = o;
         }
       }
@@ -400,14 +400,13 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(Stag
   const int r0 = pt.pr_off ? pt.pr_off[x] : 0;
   const int r1 = pt.pr_off ? pt.pr_off[x + 1] : 0;
   const size_t rowbase = size_t(2 * i + h) * pt.Jtot;
-  R qv[3] = {0, 0, 0};
-  const R* kq = nullptr;
-  if (a.kv) {
+  const bool kq = a.kv != nullptr;
+  R q0 = 0, q1 = 0, q2 = 0;
+  if (kq) {
     const R* k0 = a.kv + 3 * (a.state_off + i);
-    qv[0] = k0[0] + a.ka[0];
-    qv[1] = k0[1] + a.ka[1];
-    qv[2] = k0[2] + a.ka[2];
-    kq = qv;
+    q0 = k0[0] + a.ka[0];
+    q1 = k0[1] + a.ka[1];
+    q2 = k0[2] + a.ka[2];
   }
   const R* disp = reinterpret_cast<const R*>(pt.disp);
   if (Y) {
@@ -416,7 +415,7 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(Stag
       for (int J = jb + th; J < je; J += NTH) {
         const int e = pt.pidx[J];
         cpx<R> y = Y[rowbase + J];
-        if (kq) y = cmulc(y, bloch_phase(kq, disp + 3 * J));
+        if (kq) y = cmulc(y, bloch_phase(q0, q1, q2, disp + 3 * J));
         cpx<R>& d = pl[(e / NZ) * PZ + (e % NZ)];
         d.x += a.cre * y.x - a.cim * y.y;
         d.y += a.cre * y.y + a.cim * y.x;
@@ -430,7 +429,7 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(Stag
       for (int J = jb + th; J < je; J += NTH) {
         const int e = pt.pidx[J];
         cpx<R> o = pl[(e / NZ) * PZ + (e % NZ)];
-        if (kq) o = cmul(o, bloch_phase(kq, disp + 3 * J));
+        if (kq) o = cmul(o, bloch_phase(q0, q1, q2, disp + 3 * J));
         Wr[rowbase + J] = o;
       }
     }
@@ -488,21 +487,20 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_fwd(const cpx<R>* in
   __syncthreads();
   if (W && pt.pr_off) {
     const size_t rowbase = size_t(b) * pt.Jtot;
-    R qv[3] = {0, 0, 0};
-    const R* kq = nullptr;
-    if (kt.kv) {
+    const bool kq = kt.kv != nullptr;
+    R q0 = 0, q1 = 0, q2 = 0;
+    if (kq) {
       const R* k0 = kt.kv + 3 * (kt.state_off + b / 2);
-      qv[0] = k0[0] + kt.ka[0];
-      qv[1] = k0[1] + kt.ka[1];
-      qv[2] = k0[2] + kt.ka[2];
-      kq = qv;
+      q0 = k0[0] + kt.ka[0];
+      q1 = k0[1] + kt.ka[1];
+      q2 = k0[2] + kt.ka[2];
     }
     const R* disp = reinterpret_cast<const R*>(pt.disp);
     for (int r = pt.pr_off[x]; r < pt.pr_off[x + 1]; ++r) {
       for (int J = pt.pr_begin[r] + tid; J < pt.pr_end[r]; J += NT) {
         const int e = pt.pidx[J];
         cpx<R> o = plane[(e / NZ) * PZ + (e % NZ)];
-        if (kq) o = cmul(o, bloch_phase(kq, disp + 3 * J));
+        if (kq) o = cmul(o, bloch_phase(q0, q1, q2, disp + 3 * J));
         W[rowbase + J] = o;
       }
     }
@@ -1272,8 +1270,7 @@ __global__ __launch_bounds__(256) void k_rephase_rows(cpx<R>* __restrict__ rows,
   const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
   if (p >= total) return;
   const int J = int(p % size_t(Jtot));
-  const R q[3] = {a0, a1, a2};
-  rows[p] = cmul(rows[p], bloch_phase(q, disp + 3 * J));
+  rows[p] = cmul(rows[p], bloch_phase(a0, a1, a2, disp + 3 * J));
 }
 
 // ================================================================ launchers

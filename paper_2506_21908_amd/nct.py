@@ -99,6 +99,8 @@ def lib():
         L.nct_backward_step.restype = c_int
         L.nct_set_timing.argtypes = [c_void_p, c_int]
         L.nct_set_timing.restype = c_int
+        L.nct_set_timing_sample.argtypes = [c_void_p, c_int]
+        L.nct_set_timing_sample.restype = c_int
         L.nct_get_timing.argtypes = [c_void_p, c_int, POINTER(c_double), POINTER(ctypes.c_longlong),
                                      POINTER(c_double), POINTER(c_double)]
         L.nct_get_timing.restype = c_int
@@ -273,6 +275,10 @@ class System:
     def set_timing(self, mask: int):
         """Bit k of mask instruments kernel class k (KERNEL_CLASSES); -1 = all, 0 = off."""
         self._check(lib().nct_set_timing(self.h, int(mask)))
+
+    def set_timing_sample(self, every: int):
+        """Record one launch in every `every` of each timed class."""
+        self._check(lib().nct_set_timing_sample(self.h, int(every)))
 
     def timing(self):
         """{class: (ms, launches, algorithmic bytes, flops)} since the last set_timing."""
