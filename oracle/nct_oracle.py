@@ -18,6 +18,9 @@ Sources (paper arXiv 2506.21908, "Spin non-collinear real-time TDDFT ... INQ"):
   * Kleinman-Bylander + spin-orbit projectors    Eqs. (Vps), (Vps-soc), spinor harmonics, Sec. 3.5
   * Hartree potential                            Eq. (KSpot)
   * uniform electric (laser) pulse               Sec. 4.7, pulse profile of Figs. (fe2-laser), (fe6-laser)
+  * initial spin-density matrix (DMInitialization)  Sec. 3.2 and its algorithm figure (alg:mag_init)
+  * ground state by self-consistent imaginary-time propagation with Cholesky orthonormalisation
+    (the paper's ground-state solver is not specified; reading in the design notes)
   * k-point sampling (state index i = (n, k))    Sec. 2.1 (Eq. KSDFT), Sec. 5; states are held as
     the periodic parts u of psi = exp(i k.r) u, kinetic 1/2 |G + k|^2, projector
     Bloch phases exp(-/+ i k.d) on the sphere points; k-weights enter the occupations
@@ -673,6 +676,79 @@ def run(sysd: System, psi0: np.ndarray, nsteps: int, t0: float = 0.0, record: bo
         if record:
             rows.append(observables(sysd, psi, t))
     return psi, (np.array(rows) if record else None)
+
+
+# ----------------------------------------------------------------------------
+# initial spin-density matrix (Sec. 3.2, DMInitialization) and the ground state
+# ----------------------------------------------------------------------------
+@dataclass
+class AtomDensitySpec:
+    """Atomic charge Z (electrons) in a Gaussian of width sigma, and the atom's moment (mu_B)."""
+    Z: float
+    sigma: float
+    moment: tuple = (0.0, 0.0, 0.0)
+
+
+def dm_initialization(grid: Grid, positions: np.ndarray, atoms: List[AtomDensitySpec]) -> np.ndarray:
+    """rho_v of the initialisation algorithm: every grid point belongs to its nearest atom
+    (Voronoi partition, minimum image, ties to the lowest atom index); with d the distance to that
+    atom, n = n_a(d) = Z_a (2 pi sigma_a^2)^(-3/2) exp(-d^2 / 2 sigma_a^2) and the local
+    polarisation vector m = M_a / Z_a (the atom's moment per electron),
+    rho_v = n {(1 + m_z)/2, (1 - m_z)/2, m_x/2, -m_y/2}  (ComputeSpinDensity, Eq. density4)."""
+    X, Y, Z = np.meshgrid(grid.axis(0), grid.axis(1), grid.axis(2), indexing="ij")
+    r = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    L = np.array(grid.L, dtype=np.float64)
+    best = np.full(r.shape[0], np.inf)
+    owner = np.zeros(r.shape[0], dtype=np.int64)
+    for a, R in enumerate(np.asarray(positions, dtype=np.float64)):
+        d = r - R
+        d -= L * np.round(d / L)
+        d2 = (d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]
+        closer = d2 < best
+        best[closer] = d2[closer]
+        owner[closer] = a
+    rho = np.zeros((4, r.shape[0]))
+    for a, spec in enumerate(atoms):
+        sel = owner == a
+        n = spec.Z * (2.0 * math.pi * spec.sigma ** 2) ** -1.5 * np.exp(-best[sel] / (2.0 * spec.sigma ** 2))
+        m = np.asarray(spec.moment, dtype=np.float64) / spec.Z
+        rho[0, sel] = n * (1.0 + m[2]) / 2.0
+        rho[1, sel] = n * (1.0 - m[2]) / 2.0
+        rho[2, sel] = n * m[0] / 2.0
+        rho[3, sel] = -n * m[1] / 2.0
+    return rho.reshape((4,) + tuple(grid.n))
+
+
+def orthonormalize(psi: np.ndarray, dV: float) -> np.ndarray:
+    """Psi <- Psi L^(-H) with L L^H = dV Psi^H Psi (Cholesky): orthonormal states spanning the
+    same space (the overlap and the triangular solve are library primitives)."""
+    import scipy.linalg
+    S = psi.shape[0]
+    flat = psi.reshape(S, -1)
+    ovl = dV * (flat.conj() @ flat.T)
+    Lc = scipy.linalg.cholesky(ovl, lower=True)
+    # rows of the result: psi_new_j = sum_i psi_i (L^-H)_ij, i.e. new = (L^-H)^T flat = conj(L)^-1 flat
+    new = scipy.linalg.solve_triangular(Lc.conj(), flat, lower=True)
+    return new.reshape(psi.shape)
+
+
+def ground_state(sysd: System, psi0: np.ndarray, niter: int, tau: float,
+                 rho_init: Optional[np.ndarray] = None):
+    """Self-consistent imaginary-time propagation: each iteration applies T_K(-tau H[rho]) (the
+    Taylor polynomial of exp(-tau H), K = sysd.K) to the states, orthonormalises them, and takes
+    the new density; the first iteration uses rho_init if given (e.g. from dm_initialization).
+    Returns (psi, total energies after each iteration)."""
+    psi = orthonormalize(psi0, sysd.grid.dV)
+    rho = spin_density(psi, sysd.occ) if rho_init is None else rho_init
+    energies = []
+    for _ in range(niter):
+        F = fields_from_density(sysd, rho, 0.0)
+        H = lambda x: apply_hamiltonian(sysd, x, F)
+        psi = taylor_exp(H, psi, -1j * tau, sysd.K)
+        psi = orthonormalize(psi, sysd.grid.dV)
+        rho = spin_density(psi, sysd.occ)
+        energies.append(observables(sysd, psi, 0.0)[5])
+    return psi, np.array(energies)
 
 
 # ----------------------------------------------------------------------------

@@ -784,6 +784,83 @@ def test_velocity_gauge_ehrenfest_and_free_phase():
         assert np.allclose(cur, amp * pw, atol=1e-13)
 
 
+# ---------------------------------------------------------------- initialisation and ground state
+def test_dm_initialization_voronoi_and_moments():
+    """Every point takes its nearest atom (brute force over all atoms and periodic images), the
+    ComputeSpinDensity map of that atom's moment per electron, and for compact atomic densities
+    the integrated charge and moment are those of the atoms."""
+    grid = O.Grid((10, 10, 10), (9.0, 9.0, 9.0))
+    pos = np.array([[2.0, 2.5, 2.0], [6.5, 6.0, 7.0], [2.2, 7.0, 6.0]])
+    atoms = [O.AtomDensitySpec(6.0, 0.7, (0.0, 0.0, 3.0)), O.AtomDensitySpec(4.0, 0.6, (1.2, -1.6, 0.0)),
+             O.AtomDensitySpec(5.0, 0.65, (0.0, 2.0, -2.0))]
+    rho = O.dm_initialization(grid, pos, atoms)
+    X, Y, Z = np.meshgrid(*[grid.axis(d) for d in range(3)], indexing="ij")
+    for idx in [(0, 0, 0), (3, 4, 2), (7, 6, 8), (2, 8, 6), (9, 9, 9), (5, 5, 5)]:
+        r = np.array([X[idx], Y[idx], Z[idx]])
+        best, owner = np.inf, -1
+        for a, R in enumerate(pos):
+            for img in np.ndindex(3, 3, 3):
+                d = r - R - 9.0 * (np.array(img) - 1)
+                if d @ d < best:
+                    best, owner = d @ d, a
+        sp = atoms[owner]
+        n = sp.Z * (2 * math.pi * sp.sigma ** 2) ** -1.5 * math.exp(-best / (2 * sp.sigma ** 2))
+        m = np.array(sp.moment) / sp.Z
+        expect = n * np.array([(1 + m[2]) / 2, (1 - m[2]) / 2, m[0] / 2, -m[1] / 2])
+        assert np.allclose(rho[(slice(None),) + idx], expect, rtol=1e-13, atol=1e-300)
+    n, m = O.charge_and_magnetization(rho)
+    assert abs(n.sum() * grid.dV - 15.0) < 0.02
+    assert np.allclose(m.reshape(3, -1).sum(1) * grid.dV, [1.2, 0.4, 1.0], atol=0.01)
+
+
+def test_orthonormalize_complex_overlap():
+    rng = np.random.default_rng(3)
+    psi = rng.standard_normal((4, 2, 3, 3, 3)) + 1j * rng.standard_normal((4, 2, 3, 3, 3))
+    out = O.orthonormalize(psi, 0.7)
+    f, g = out.reshape(4, -1), psi.reshape(4, -1)
+    assert np.abs(0.7 * f.conj() @ f.T - np.eye(4)).max() < 1e-13
+    # same span: the projector onto the states is unchanged
+    P1 = f.T @ np.linalg.pinv(f.T)
+    P0 = g.T @ np.linalg.pinv(g.T)
+    assert np.abs(P1 - P0).max() < 1e-12
+
+
+def test_ground_state_reaches_lowest_eigenvectors_without_interactions():
+    """xc = 0, no Hartree, static B, SOC projectors: imaginary-time iterations converge to the
+    lowest eigenvectors of the dense Hamiltonian (band energy and spanned space)."""
+    # two states: the spectrum of this system has a 0.56 Ha gap above its second level
+    w = I.make_system(n=(6, 6, 6), L=(5.0,) * 3, nstates=2, natoms=1, case=61, xc=0, hartree=0,
+                      bfield=I.BField(B0=(0.0, 0.05, 0.1)), full_spinors=True)
+    sysd = O.system_from_workload(w)
+    F = O.fields_from_density(sysd, O.spin_density(w.psi0, sysd.occ), 0.0)
+    Hd = _dense_H(sysd, F.v, F.b)
+    evals, evecs = np.linalg.eigh(Hd)
+    assert evals[2] - evals[1] > 0.5
+    psi, E = O.ground_state(sysd, w.psi0, 400, 0.1)
+    assert abs(E[-1] - evals[:2].sum()) < 1e-9
+    assert np.all(np.diff(E[5:]) < 1e-12)                   # the energy decreases
+    f = psi.reshape(2, -1).T * math.sqrt(sysd.grid.dV)
+    P = f @ f.conj().T
+    Q = evecs[:, :2] @ evecs[:, :2].conj().T
+    assert np.abs(P - Q).max() < 1e-6
+
+
+def test_ground_state_self_consistent_with_exchange_and_hartree():
+    """With exchange and Hartree on, the converged states are eigenvectors of the Hamiltonian built
+    from their own density (subspace residual H psi - psi Lambda), and the energy settles."""
+    w = I.make_system(n=(6, 6, 6), L=(5.0,) * 3, nstates=2, natoms=1, case=61, xc=1, hartree=1,
+                      bfield=I.BField(B0=(0.0, 0.05, 0.1)), full_spinors=True)
+    sysd = O.system_from_workload(w)
+    psi, E = O.ground_state(sysd, w.psi0, 400, 0.1)
+    F = O.fields_from_density(sysd, O.spin_density(psi, sysd.occ), 0.0)
+    f = psi.reshape(2, -1)
+    hf = O.apply_hamiltonian(sysd, psi, F).reshape(2, -1)
+    Lam = sysd.grid.dV * f.conj() @ hf.T
+    assert np.abs(Lam - Lam.conj().T).max() < 1e-12
+    assert np.abs(hf - Lam.T @ f).max() < 1e-6 * np.abs(hf).max()
+    assert abs(E[-1] - E[-2]) < 1e-12
+
+
 # ---------------------------------------------------------------- gradient oracle
 def test_tangent_linear_gradient_matches_central_differences():
     bf = I.BField(pulses=I.circular_pulses([0.1, 0.2], [0.5, 1.0], 0.05, 0.1))
