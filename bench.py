@@ -25,6 +25,7 @@ HBM_PEAK_GBS = 8000.0
 # 12 plane passes of a step, so every stage position is sampled); each recorded launch costs the
 # stream ~10 us.
 TIMING_STRIDE = 5
+GS_TAU = 0.02  # imaginary-time step: tau |H_max| ~ 1.7 at h = 0.42 bohr, inside T_4's stable range
 XC_NAMES = {0: "none", 1: "Slater exchange, locally collinear",
             2: "Slater exchange + PW92 correlation (LSDA), locally collinear"}
 WORKLOADS = {"tiny": 0, "cluster": 1, "solid": 2, "grad": 3, "large": 4, "laser": 5, "kpoints": 6}
@@ -104,6 +105,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32-mixed comparison run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--adjoint-segment", type=int, default=10)
+    ap.add_argument("--no-ground-state", action="store_true", help="skip the ground-state timing")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB device copy first (PMC scale reference)")
     args = ap.parse_args()
@@ -249,6 +251,27 @@ def main():
                           "definition": "(taped re-run of the segment + backward steps) / forward steps"}
         s.close()
         del psi, psi_c, lam
+        torch.cuda.empty_cache()
+    if not args.no_ground_state and w.natoms > 0 and w.xc <= 2:
+        # ground state by imaginary time from the initial spin-density matrix (10 iterations)
+        s = nct.system_from_workload(w, precision=pflag)
+        dens = I.atom_densities(w)
+        psi = nct.states_to_device(w.psi0, pflag)
+        # one untimed iteration sets up the BLAS handle and its kernels
+        s.dm_initialization(dens, update_fields=True)
+        s.ground_state(psi.clone(), 1, GS_TAU, keep_fields=True)
+        s.dm_initialization(dens, update_fields=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E = s.ground_state(psi, 10, GS_TAU, keep_fields=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out["ground_state"] = {"iterations_per_s": 10 / el, "tau": GS_TAU,
+                               "energy_first": float(E[0]), "energy_last": float(E[-1]),
+                               "definition": "imaginary-time iteration: T_K(-tau H) on all states, "
+                                             "Cholesky orthonormalisation, density and fields"}
+        s.close()
+        del psi
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)

@@ -155,6 +155,45 @@ typedef struct {
  * a non-finite parameter. */
 nct_status nct_set_laser(nct_system *sys, int npulses, const nct_laser_pulse *pulses);
 
+/* Atomic data of the initial spin-density matrix (initialisation algorithm of Sec. 3.2): the
+ * atom's charge Z (electrons) spread as a Gaussian of width sigma (bohr) and its magnetic moment
+ * (mu_B, |moment| <= Z). */
+typedef struct {
+  double Z;
+  double sigma;
+  double moment[3];
+} nct_atom_density;
+
+/* Initial spin-density matrix (Sec. 3.2, DMInitialization): every grid point belongs to its
+ * nearest atom (Voronoi partition with the minimum-image distance d, ties to the lowest index);
+ * there n = Z (2 pi sigma^2)^(-3/2) exp(-d^2 / 2 sigma^2), the local polarisation vector is
+ * m = moment / Z (the atom's moment per electron), and
+ * rho_v = n {(1 + m_z)/2, (1 - m_z)/2, m_x/2, -m_y/2} (Eq. density4).
+ *   atoms        host [params.natoms], in the order of params.positions;
+ *   rho_v_dev    device double [4][N] receives rho_v, or NULL;
+ *   update_fields nonzero: the system's fields become those of this density (self-consistent
+ *                mode only), e.g. to start nct_ground_state from it.
+ * Synchronises the stream.  Errors: NCT_ERR_ARG (no atoms, NULL atoms, Z or sigma not positive,
+ * |moment| > Z), NCT_ERR_STATE (update_fields with frozen fields). */
+nct_status nct_dm_initialization(nct_system *sys, const nct_atom_density *atoms, double *rho_v_dev,
+                                 int update_fields);
+
+/* Ground state by self-consistent imaginary-time propagation (the paper does not specify its
+ * solver): psi is first orthonormalised, then every iteration forms T_K(-tau H[rho]) psi (the
+ * Taylor polynomial of exp(-tau H) of order params.taylor_order, through the same kernels as
+ * the real-time step), orthonormalises it (Cholesky of the state overlap; the overlap and the
+ * triangular transform are complex GEMMs of rocBLAS, the S x S factorisation runs on the host)
+ * and recomputes rho and the fields from it.  keep_fields nonzero: the first iteration uses the
+ * system's current fields (e.g. from nct_dm_initialization); 0: those of psi's own density.
+ * With frozen fields they stay frozen.  energies_host, if non-NULL, receives [niter] total
+ * energies (the E_total of nct_step's observables).  B_ext is taken at t = 0.  tau must keep
+ * tau |H| within the stability range of the Taylor polynomial (|T_4(-x)| < 1 for x < 2.78).
+ * Synchronises the stream.  Errors: NCT_ERR_ARG (niter < 0, tau not positive), NCT_ERR_NONFINITE
+ * (states linearly dependent, or a non-finite energy), NCT_ERR_UNSUPPORTED (more than 4096
+ * states). */
+nct_status nct_ground_state(nct_system *sys, void *psi_dev, int niter, double tau, int keep_fields,
+                            double *energies_host);
+
 /* Gauge of the laser set by nct_set_laser.
  *   NCT_GAUGE_LENGTH (default): v_E = E(t).(r - c) as described there (isolated systems);
  *   NCT_GAUGE_VELOCITY: for periodic systems; every state's kinetic momentum is shifted by the

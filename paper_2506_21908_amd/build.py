@@ -4,6 +4,8 @@ import shutil
 import subprocess
 import sys
 
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnct.so")
@@ -49,7 +51,8 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
         msg = "\n".join(f"--- {s} ---\n{o}" for s, o in failed)
         raise RuntimeError("hipcc failed:\n" + msg)
     tmp = LIB + ".tmp"
-    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + [
+        "-L", os.path.join(ROCM, "lib"), "-lrocblas", "-Wl,-rpath," + os.path.join(ROCM, "lib")]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

@@ -4,6 +4,7 @@
 // |G|^2 per axis), the projector tables of every atom, and drives the
 // kernels of one ETRS step on the caller's stream.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -101,6 +102,13 @@ struct nct_system {
   double* ftot = nullptr;      // [kFieldTot]
   double* epart = nullptr;     // [2S][ntiles][2]
   double* obs_dev = nullptr;   // [cap][13]
+  // ground state: rocBLAS handle (plain library GEMMs of the orthonormalisation), S x S buffers
+  rocblas_handle blas = nullptr;
+  void* ovl = nullptr;         // complex R [S][S] overlap / triangular factor
+  double* dm_atoms = nullptr;  // [natoms][9] atom data of the initial spin-density matrix
+  void* ovl_part = nullptr;    // complex R [nb][S][S] split-K partial overlaps
+  void* ovl_ones = nullptr;    // complex R [nb] ones
+  int ovl_nb = 0;
   int obs_cap = 0;
 
   // device: psi-sized work (precision of the system)
@@ -590,6 +598,93 @@ void bfield_jac(const nct_system* s, double t, std::vector<double>& out) {
   }
 }
 
+// ---------------------------------------------------------------- S x S host linear algebra
+// A (column-major, Hermitian positive definite) = L L^H; on return A holds M = L^(-H) (upper
+// triangular), so that Psi M has orthonormal columns when A is their overlap.  False if A is not
+// positive definite.
+bool cholesky_inverse_h(std::vector<std::complex<double>>& A, int n) {
+  using C = std::complex<double>;
+  std::vector<C> L(size_t(n) * n, C(0, 0));
+  auto a = [&](int i, int j) -> C& { return A[size_t(i) + size_t(j) * n]; };
+  auto l = [&](int i, int j) -> C& { return L[size_t(i) + size_t(j) * n]; };
+  for (int j = 0; j < n; ++j) {
+    double d = a(j, j).real();
+    for (int k = 0; k < j; ++k) d -= std::norm(l(j, k));
+    // a pivot that rounding alone can produce means linearly dependent columns
+    if (!(d > 1e-12 * std::fabs(a(j, j).real())) || !std::isfinite(d)) return false;
+    const double ljj = std::sqrt(d);
+    l(j, j) = C(ljj, 0);
+    for (int i = j + 1; i < n; ++i) {
+      C acc = a(i, j);
+      for (int k = 0; k < j; ++k) acc -= l(i, k) * std::conj(l(j, k));
+      l(i, j) = acc / ljj;
+    }
+  }
+  // M = L^(-H): solve L^H m_j = e_j by back substitution ((L^H)(i, k) = conj(L(k, i)))
+  for (int j = 0; j < n; ++j) {
+    for (int i = n - 1; i >= 0; --i) {
+      C acc = (i == j) ? C(1, 0) : C(0, 0);
+      for (int k = i + 1; k < n; ++k) acc -= std::conj(l(k, i)) * a(k, j);
+      a(i, j) = acc / std::conj(l(i, i));
+    }
+  }
+  return true;
+}
+
+// complex GEMM of the orthonormalisation through rocBLAS (plain library GEMMs)
+template <typename R>
+struct Blas;
+template <>
+struct Blas<double> {
+  using C = rocblas_double_complex;
+  static rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb,
+                             rocblas_int m, rocblas_int n, rocblas_int k, const C* al, const void* A,
+                             rocblas_int lda, const void* B, rocblas_int ldb, const C* be, void* Cm,
+                             rocblas_int ldc) {
+    return rocblas_zgemm(h, ta, tb, m, n, k, al, static_cast<const C*>(A), lda,
+                         static_cast<const C*>(B), ldb, be, static_cast<C*>(Cm), ldc);
+  }
+  static rocblas_status gemm_sb(rocblas_handle h, rocblas_operation ta, rocblas_operation tb,
+                                rocblas_int m, rocblas_int n, rocblas_int k, const C* al, const void* A,
+                                rocblas_int lda, rocblas_stride sa, const void* B, rocblas_int ldb,
+                                rocblas_stride sb, const C* be, void* Cm, rocblas_int ldc,
+                                rocblas_stride sc, rocblas_int batch) {
+    return rocblas_zgemm_strided_batched(h, ta, tb, m, n, k, al, static_cast<const C*>(A), lda, sa,
+                                         static_cast<const C*>(B), ldb, sb, be, static_cast<C*>(Cm),
+                                         ldc, sc, batch);
+  }
+  static rocblas_status gemv(rocblas_handle h, rocblas_int m, rocblas_int n, const C* al, const void* A,
+                             rocblas_int lda, const void* x, const C* be, void* y) {
+    return rocblas_zgemv(h, rocblas_operation_none, m, n, al, static_cast<const C*>(A), lda,
+                         static_cast<const C*>(x), 1, be, static_cast<C*>(y), 1);
+  }
+};
+template <>
+struct Blas<float> {
+  using C = rocblas_float_complex;
+  static rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb,
+                             rocblas_int m, rocblas_int n, rocblas_int k, const C* al, const void* A,
+                             rocblas_int lda, const void* B, rocblas_int ldb, const C* be, void* Cm,
+                             rocblas_int ldc) {
+    return rocblas_cgemm(h, ta, tb, m, n, k, al, static_cast<const C*>(A), lda,
+                         static_cast<const C*>(B), ldb, be, static_cast<C*>(Cm), ldc);
+  }
+  static rocblas_status gemm_sb(rocblas_handle h, rocblas_operation ta, rocblas_operation tb,
+                                rocblas_int m, rocblas_int n, rocblas_int k, const C* al, const void* A,
+                                rocblas_int lda, rocblas_stride sa, const void* B, rocblas_int ldb,
+                                rocblas_stride sb, const C* be, void* Cm, rocblas_int ldc,
+                                rocblas_stride sc, rocblas_int batch) {
+    return rocblas_cgemm_strided_batched(h, ta, tb, m, n, k, al, static_cast<const C*>(A), lda, sa,
+                                         static_cast<const C*>(B), ldb, sb, be, static_cast<C*>(Cm),
+                                         ldc, sc, batch);
+  }
+  static rocblas_status gemv(rocblas_handle h, rocblas_int m, rocblas_int n, const C* al, const void* A,
+                             rocblas_int lda, const void* x, const C* be, void* y) {
+    return rocblas_cgemv(h, rocblas_operation_none, m, n, al, static_cast<const C*>(A), lda,
+                         static_cast<const C*>(x), 1, be, static_cast<C*>(y), 1);
+  }
+};
+
 // ---------------------------------------------------------------- engine
 template <typename R>
 struct Engine {
@@ -838,6 +933,9 @@ struct Engine {
                  "plane_stage");
   }
 
+  // imaginary time: when > 0, taylor() forms T_K(-imag_tau H) x (real Horner coefficients)
+  double imag_tau = 0.0;
+
   // T_K(-i a H) x by Horner stages w_k = x + (-i a/(K-k+1)) H w_{k-1}, w_0 = x.
   // stage_out[k-1] (k = 1..K-1), if given, receives w_k (the adjoint tape); else the work buffer.
   // kin_save: keep the first stage's column pass in this buffer; kin_reuse: take the first
@@ -868,8 +966,13 @@ struct Engine {
       sa.w_in = cw;
       sa.x_base = x;
       sa.alpha = R(1);
-      sa.cre = R(0);
-      sa.cim = R(-a / double(K - k + 1));
+      if (imag_tau > 0.0) {
+        sa.cre = R(-imag_tau / double(K - k + 1));
+        sa.cim = R(0);
+      } else {
+        sa.cre = R(0);
+        sa.cim = R(-a / double(K - k + 1));
+      }
       sa.w_out = last ? out : (stage_out ? stage_out[k - 1] : s->wbuf);
       sa.tmp_out = last ? outhat : s->tmp;
       sa.W = s->natoms ? (last ? outW : s->Wwork) : nullptr;
@@ -1184,6 +1287,117 @@ struct Engine {
     return NCT_OK;
   }
 
+  // ------------------------------------------------------------ ground state
+  nct_status ensure_blas() {
+    if (s->ovl_ones) return NCT_OK;  // set last: a failed set-up is redone on the next call
+    if (!s->blas) {
+      if (rocblas_create_handle(&s->blas) != rocblas_status_success) {
+        s->blas = nullptr;
+        return fail(s, NCT_ERR_HIP, "rocblas_create_handle failed");
+      }
+      if (rocblas_set_stream(s->blas, s->st) != rocblas_status_success)
+        return fail(s, NCT_ERR_HIP, "rocblas_set_stream failed");
+    }
+    nct_status r;
+    if (!s->ovl && (r = dalloc(s, size_t(s->S) * s->S * 16, &s->ovl)) != NCT_OK) return r;
+    // split-K of the overlap: up to 256 chunks, partials within 4 Mi complex entries
+    const size_t SS = size_t(s->S) * s->S;
+    size_t nb = std::min<size_t>(256, std::max<size_t>(1, (size_t(1) << 22) / SS));
+    nb = std::min<size_t>(nb, std::max<size_t>(1, 2 * s->N / 64));
+    s->ovl_nb = int(nb);
+    if (!s->ovl_part && (r = dalloc(s, nb * SS * sizeof(cpx<R>), &s->ovl_part)) != NCT_OK) return r;
+    void* ones_d = nullptr;
+    if ((r = dalloc(s, nb * sizeof(cpx<R>), &ones_d)) != NCT_OK) return r;
+    std::vector<cpx<R>> ones(nb, cpx<R>{R(1), R(0)});
+    HIPCHK(s, hipMemcpy(ones_d, ones.data(), nb * sizeof(cpx<R>), hipMemcpyHostToDevice));
+    s->ovl_ones = ones_d;
+    return NCT_OK;
+  }
+
+  // dst = src L^(-H), L L^H = dV src^H src (states as the columns of a 2N x S matrix)
+  nct_status orthonormalize(const void* src, void* dst) {
+    nct_status r;
+    if ((r = ensure_blas()) != NCT_OK) return r;
+    using C = typename Blas<R>::C;
+    const rocblas_int S = s->S, K2 = rocblas_int(2 * s->N);
+    const C al(R(s->dV), R(0)), one(R(1), R(0)), zero(R(0), R(0));
+    // overlap dV src^H src: k = 2N is long and S x S small, so split K into nb strided chunks
+    // (one GEMM batch each), fold the remainder into chunk 0, and sum the partials with a GEMV
+    const rocblas_int nb = s->ovl_nb;
+    const rocblas_int kc = K2 / nb, krem = K2 - kc * nb;
+    const rocblas_stride SS = rocblas_stride(S) * S;
+    const C* A0 = static_cast<const C*>(src);
+    rocblas_status bs = Blas<R>::gemm_sb(s->blas, rocblas_operation_conjugate_transpose,
+                                         rocblas_operation_none, S, S, kc, &one, A0, K2, kc, A0, K2, kc,
+                                         &zero, s->ovl_part, S, SS, nb);
+    if (bs == rocblas_status_success && krem > 0)
+      bs = Blas<R>::gemm(s->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, S, S,
+                         krem, &one, A0 + size_t(kc) * nb, K2, A0 + size_t(kc) * nb, K2, &one,
+                         s->ovl_part, S);
+    if (bs == rocblas_status_success)
+      bs = Blas<R>::gemv(s->blas, rocblas_int(SS), nb, &al, s->ovl_part, rocblas_int(SS), s->ovl_ones,
+                         &zero, s->ovl);
+    if (bs != rocblas_status_success) return fail(s, NCT_ERR_HIP, "rocBLAS overlap: status %d", int(bs));
+    std::vector<cpx<R>> h(size_t(S) * S);
+    HIPCHK(s, hipMemcpyAsync(h.data(), s->ovl, h.size() * sizeof(cpx<R>), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    std::vector<std::complex<double>> A(h.size());
+    for (size_t k = 0; k < h.size(); ++k) A[k] = std::complex<double>(double(h[k].x), double(h[k].y));
+    if (!cholesky_inverse_h(A, S))
+      return fail(s, NCT_ERR_NONFINITE, "overlap of the states is not positive definite");
+    for (size_t k = 0; k < h.size(); ++k) h[k] = cpx<R>{R(A[k].real()), R(A[k].imag())};
+    HIPCHK(s, hipMemcpyAsync(s->ovl, h.data(), h.size() * sizeof(cpx<R>), hipMemcpyHostToDevice, s->st));
+    bs = Blas<R>::gemm(s->blas, rocblas_operation_none, rocblas_operation_none, K2, S, S, &one, src, K2,
+                       s->ovl, S, &zero, dst, K2);
+    if (bs != rocblas_status_success) return fail(s, NCT_ERR_HIP, "rocBLAS transform GEMM: status %d", int(bs));
+    HIPCHK(s, hipStreamSynchronize(s->st));  // h is released on return
+    return NCT_OK;
+  }
+
+  // Self-consistent imaginary-time iterations: psi <- orthonormalise(T_K(-tau H[rho]) psi),
+  // rho <- rho(psi); energies[it] = total energy after iteration it.
+  nct_status ground_state(void* psi, int niter, double tau, bool keep_fields, double* energies) {
+    nct_status r;
+    if ((r = orthonormalize(psi, s->phi)) != NCT_OK) return r;
+    HIPCHK(s, hipMemcpyAsync(psi, s->phi, psiB(), hipMemcpyDeviceToDevice, s->st));
+    if (s->frozen) {
+      if (!s->fields_valid) return fail(s, NCT_ERR_STATE, "no fields");
+    } else if (!(keep_fields && s->fields_valid)) {
+      if ((r = density(psi)) != NCT_OK) return r;
+      if ((r = fields_from_rho(true)) != NCT_OK) return r;
+    }
+    if (s->obs_cap < niter) {
+      void* p;
+      if ((r = dalloc(s, size_t(niter) * kObsWidth * sizeof(double), &p)) != NCT_OK) return r;
+      s->obs_dev = static_cast<double*>(p);
+      s->obs_cap = niter;
+    }
+    imag_tau = tau;
+    for (int it = 0; it < niter; ++it) {
+      at_time(0.0);
+      if ((r = prepare(psi, s->psihat, s->Wpsi)) != NCT_OK) break;
+      if ((r = taylor(psi, s->psihat, s->Wpsi, s->phi, nullptr, nullptr, 0.0)) != NCT_OK) break;
+      if ((r = orthonormalize(s->phi, psi)) != NCT_OK) break;
+      if ((r = density(psi)) != NCT_OK) break;
+      if ((r = fields_from_rho(!s->frozen)) != NCT_OK) break;
+      if ((r = prepare(psi, s->psihat, s->Wpsi)) != NCT_OK) break;
+      if ((r = obs_row(0.0, s->obs_dev + size_t(it) * kObsWidth)) != NCT_OK) break;
+    }
+    imag_tau = 0.0;
+    if (r != NCT_OK) return r;
+    std::vector<double> rows(size_t(niter) * kObsWidth);
+    if (niter > 0)
+      HIPCHK(s, hipMemcpyAsync(rows.data(), s->obs_dev, rows.size() * sizeof(double), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    harvest_timing(s);
+    for (int it = 0; it < niter; ++it) {
+      const double e = rows[size_t(it) * kObsWidth + 5];
+      if (!std::isfinite(e)) return fail(s, NCT_ERR_NONFINITE, "non-finite energy at iteration %d", it);
+      if (energies) energies[it] = e;
+    }
+    return NCT_OK;
+  }
+
   nct_status apply(const void* psi, void* hpsi, double t) {
     nct_status r;
     at_time(t);
@@ -1283,6 +1497,10 @@ nct_status alloc_tape(nct_system* s, nct_system::Tape& T, int cap) {
 void free_all(nct_system* s) {
   for (hipStream_t q : {s->st2, s->stB, s->stB2})
     if (q) (void)hipStreamSynchronize(q);
+  if (s->blas) {
+    (void)rocblas_destroy_handle(s->blas);
+    s->blas = nullptr;
+  }
   for (auto& b : s->owned) (void)hipFree(b.p);
   s->owned.clear();
   for (hipEvent_t* e : {&s->ev_rows, &s->ev_proj, &s->evB_rows, &s->evB_proj, &s->ev_fork, &s->ev_join}) {
@@ -1480,6 +1698,60 @@ void nct_destroy_system(nct_system* sys) {
 
 const char* nct_last_error(const nct_system* sys) {
   return sys ? sys->err.c_str() : g_create_error.c_str();
+}
+
+nct_status nct_dm_initialization(nct_system* s, const nct_atom_density* atoms, double* rho_v_dev,
+                                 int update_fields) {
+  if (!s) return NCT_ERR_ARG;
+  const int na = s->prm.natoms;
+  if (na <= 0) return fail(s, NCT_ERR_ARG, "the system has no atoms");
+  if (!atoms) return fail(s, NCT_ERR_ARG, "atoms is NULL");
+  if (update_fields && s->frozen) return fail(s, NCT_ERR_STATE, "fields are frozen");
+  std::vector<double> a6(size_t(na) * 6), m3(size_t(na) * 3);
+  for (int a = 0; a < na; ++a) {
+    const nct_atom_density& q = atoms[a];
+    const double mm = std::sqrt(q.moment[0] * q.moment[0] + q.moment[1] * q.moment[1] + q.moment[2] * q.moment[2]);
+    if (!(q.Z > 0) || !(q.sigma > 0) || !std::isfinite(q.Z) || !std::isfinite(q.sigma) || !std::isfinite(mm))
+      return fail(s, NCT_ERR_ARG, "atom %d: Z and sigma must be positive and finite", a);
+    if (mm > q.Z * (1.0 + 1e-12)) return fail(s, NCT_ERR_ARG, "atom %d: |moment| exceeds Z", a);
+    for (int k = 0; k < 3; ++k) {
+      a6[6 * size_t(a) + k] = s->positions_h[3 * size_t(a) + k];
+      m3[3 * size_t(a) + k] = q.moment[k];
+    }
+    a6[6 * size_t(a) + 3] = q.Z;
+    a6[6 * size_t(a) + 4] = q.sigma;
+    a6[6 * size_t(a) + 5] = 0.0;
+  }
+  nct_status r;
+  if (!s->dm_atoms) {
+    void* p;
+    if ((r = dalloc(s, size_t(na) * 9 * sizeof(double), &p)) != NCT_OK) return r;
+    s->dm_atoms = static_cast<double*>(p);
+  }
+  double* d_a = s->dm_atoms;
+  double* d_m = s->dm_atoms + size_t(na) * 6;
+  HIPCHK(s, hipMemcpyAsync(d_a, a6.data(), a6.size() * sizeof(double), hipMemcpyHostToDevice, s->st));
+  HIPCHK(s, hipMemcpyAsync(d_m, m3.data(), m3.size() * sizeof(double), hipMemcpyHostToDevice, s->st));
+  HIPCHK(s, launch_dm_init(s->n, s->prm.cell, na, d_a, d_m, s->rho, s->st));
+  if (rho_v_dev)
+    HIPCHK(s, hipMemcpyAsync(rho_v_dev, s->rho, 4 * s->N * 8, hipMemcpyDeviceToDevice, s->st));
+  if (update_fields) {
+    if (s->fp64) r = Engine<double>{s}.fields_from_rho(true);
+    else r = Engine<float>{s}.fields_from_rho(true);
+    if (r != NCT_OK) return r;
+  }
+  HIPCHK(s, hipStreamSynchronize(s->st));
+  return NCT_OK;
+}
+
+nct_status nct_ground_state(nct_system* s, void* psi, int niter, double tau, int keep_fields,
+                            double* energies_host) {
+  if (!s || !psi) return s ? fail(s, NCT_ERR_ARG, "psi is NULL") : NCT_ERR_ARG;
+  if (niter < 0) return fail(s, NCT_ERR_ARG, "niter < 0");
+  if (!(tau > 0) || !std::isfinite(tau)) return fail(s, NCT_ERR_ARG, "tau must be positive and finite");
+  if (s->S > 4096) return fail(s, NCT_ERR_UNSUPPORTED, "at most 4096 states in the ground-state solver");
+  if (s->fp64) return Engine<double>{s}.ground_state(psi, niter, tau, keep_fields != 0, energies_host);
+  return Engine<float>{s}.ground_state(psi, niter, tau, keep_fields != 0, energies_host);
 }
 
 nct_status nct_set_laser_gauge(nct_system* s, int gauge) {

@@ -177,6 +177,14 @@ struct LaunchEvents {
 };
 LaunchEvents& launch_events();
 
+// Initial spin-density matrix (initialisation algorithm of Sec. 3.2): every grid point takes its
+// nearest atom (minimum image, ties to the lowest index; squared distances formed without fused
+// operations), n = Z_a (2 pi s_a^2)^(-3/2) exp(-d^2 / 2 s_a^2), m = M_a / Z_a, and
+// rho_v = n {(1 + m_z)/2, (1 - m_z)/2, m_x/2, -m_y/2}.  atoms: device double [natoms][6]
+// {X, Y, Z position, charge, sigma, unused} and moments [natoms][3].
+hipError_t launch_dm_init(const int n[3], const double cell[3], int natoms, const double* atoms,
+                          const double* moments, double* rho, hipStream_t st);
+
 bool plane_pair_supported(int ny, int nz);
 bool line_supported(int n);
 

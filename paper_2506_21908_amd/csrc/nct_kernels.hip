@@ -1273,6 +1273,45 @@ __global__ __launch_bounds__(256) void k_rephase_rows(cpx<R>* __restrict__ rows,
   rows[p] = cmul(rows[p], bloch_phase(a0, a1, a2, disp + 3 * J));
 }
 
+// ---------------------------------------------------------------- initial spin-density matrix
+__global__ __launch_bounds__(256) void k_dm_init(int nx, int ny, int nz, double hx, double hy,
+                                                 double hz, double Lx, double Ly, double Lz, int natoms,
+                                                 const double* __restrict__ atoms,
+                                                 const double* __restrict__ moments,
+                                                 double* __restrict__ rho) {
+  const size_t N = size_t(nx) * ny * nz;
+  const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p >= N) return;
+  const size_t nyz = size_t(ny) * nz;
+  const int ix = int(p / nyz);
+  const int rem = int(p - size_t(ix) * nyz);
+  const int iy = rem / nz, iz = rem - (rem / nz) * nz;
+  const double r[3] = {ix * hx, iy * hy, iz * hz};
+  const double L[3] = {Lx, Ly, Lz};
+  double best = 1e300;
+  int owner = 0;
+  for (int a = 0; a < natoms; ++a) {
+    double d2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double d = __dsub_rn(r[k], atoms[6 * a + k]);
+      d = __dsub_rn(d, __dmul_rn(L[k], rint(d / L[k])));
+      d2 = __dadd_rn(d2, __dmul_rn(d, d));
+    }
+    if (d2 < best) {
+      best = d2;
+      owner = a;
+    }
+  }
+  const double Z = atoms[6 * owner + 3], sg = atoms[6 * owner + 4];
+  const double n = Z * pow(2.0 * 3.14159265358979323846 * sg * sg, -1.5) * exp(-best / (2.0 * sg * sg));
+  const double mx = moments[3 * owner] / Z, my = moments[3 * owner + 1] / Z, mz = moments[3 * owner + 2] / Z;
+  rho[p] = n * (1.0 + mz) / 2.0;
+  rho[N + p] = n * (1.0 - mz) / 2.0;
+  rho[2 * N + p] = n * mx / 2.0;
+  rho[3 * N + p] = -n * my / 2.0;
+}
+
 // ================================================================ launchers
 static inline unsigned nblocks(size_t n, unsigned bs) { return unsigned((n + bs - 1) / bs); }
 
@@ -1378,6 +1417,14 @@ hipError_t launch_plane_fwd(const int n[3], int B, const void* in, void* out, vo
   NCT_PLANE_PAIRS(X)
 #undef X
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_dm_init(const int n[3], const double cell[3], int natoms, const double* atoms,
+                          const double* moments, double* rho, hipStream_t st) {
+  const size_t N = size_t(n[0]) * n[1] * n[2];
+  nct_launch(k_dm_init, dim3(nblocks(N, 256)), dim3(256), 0, st, n[0], n[1], n[2], cell[0] / n[0],
+             cell[1] / n[1], cell[2] / n[2], cell[0], cell[1], cell[2], natoms, atoms, moments, rho);
+  return hipGetLastError();
 }
 
 template <typename R>

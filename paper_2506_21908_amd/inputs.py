@@ -318,6 +318,24 @@ def monkhorst_pack(L, grid=(2, 2, 2)) -> np.ndarray:
     return np.array([[a, b, c] for a in axes[0] for b in axes[1] for c in axes[2]])
 
 
+@dataclasses.dataclass
+class AtomDensity:
+    """Atomic charge Z in a Gaussian of width sigma and the atom's moment (initial spin density)."""
+    Z: float
+    sigma: float
+    moment: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+
+
+def atom_densities(w, Z: float = 4.0, sigma: float = 1.0, tilt_deg: float = 30.0):
+    """Initial atomic data for a workload: the states' electrons shared over the atoms, each with a
+    moment of half its charge along the 30-degree tilt of the initial spinors."""
+    na = max(len(w.positions), 1)
+    Zs = float(np.sum(w.occ)) / na if Z is None else Z
+    t = math.radians(tilt_deg)
+    mom = (0.5 * Zs * math.sin(t), 0.0, 0.5 * Zs * math.cos(t))
+    return [AtomDensity(Zs, sigma, mom) for _ in range(na)]
+
+
 def circular_pulses(t_centers: Sequence[float], omegas: Sequence[float], A: float, tau: float):
     return [Pulse(A=A, omega=w, t0=t, tau=tau) for t, w in zip(t_centers, omegas)]
 

@@ -39,6 +39,10 @@ class BField(ctypes.Structure):
     _fields_ = [("B0", c_double * 3), ("npulses", c_int), ("pulses", POINTER(Pulse))]
 
 
+class AtomDensity(ctypes.Structure):
+    _fields_ = [("Z", c_double), ("sigma", c_double), ("moment", c_double * 3)]
+
+
 class LaserPulse(ctypes.Structure):
     _fields_ = [("A", c_double), ("omega", c_double), ("t0", c_double), ("tau", c_double),
                 ("phase", c_double), ("pol", c_double * 3)]
@@ -83,6 +87,10 @@ def lib():
         L.nct_set_kpoints.restype = c_int
         L.nct_set_laser_gauge.argtypes = [c_void_p, c_int]
         L.nct_set_laser_gauge.restype = c_int
+        L.nct_dm_initialization.argtypes = [c_void_p, POINTER(AtomDensity), c_void_p, c_int]
+        L.nct_dm_initialization.restype = c_int
+        L.nct_ground_state.argtypes = [c_void_p, c_void_p, c_int, c_double, c_int, POINTER(c_double)]
+        L.nct_ground_state.restype = c_int
         L.nct_density_magnetization.argtypes = [c_void_p, c_void_p, c_double, c_void_p,
                                                 POINTER(c_double), c_int]
         L.nct_density_magnetization.restype = c_int
@@ -227,6 +235,22 @@ class System:
             arr[k] = LaserPulse(q.A, q.omega, q.t0, q.tau, getattr(q, "phase", 0.0),
                                 (c_double * 3)(*q.pol))
         self._check(lib().nct_set_laser(self.h, len(pl), ctypes.cast(arr, POINTER(LaserPulse)) if pl else None))
+
+    def dm_initialization(self, atoms, rho_v=None, update_fields: bool = True):
+        """Initial spin-density matrix from per-atom (Z, sigma, moment) (objects with those
+        attributes, in the order of the atom positions)."""
+        arr = (AtomDensity * max(1, len(atoms)))()
+        for k, a in enumerate(atoms):
+            arr[k] = AtomDensity(a.Z, a.sigma, (c_double * 3)(*a.moment))
+        self._check(lib().nct_dm_initialization(self.h, ctypes.cast(arr, POINTER(AtomDensity)),
+                                                _tptr(rho_v), int(update_fields)))
+
+    def ground_state(self, psi, niter: int, tau: float, keep_fields: bool = False):
+        """Imaginary-time ground state in place; returns the total energy after each iteration."""
+        e = np.zeros(max(int(niter), 1))
+        self._check(lib().nct_ground_state(self.h, _tptr(psi), int(niter), float(tau),
+                                           int(keep_fields), _dptr(e)))
+        return e[:int(niter)]
 
     def set_laser_gauge(self, gauge: str):
         """"length" (isolated systems) or "velocity" (periodic systems)."""

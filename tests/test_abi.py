@@ -23,7 +23,8 @@ def test_header_declares_the_boundary():
     for f in ["nct_create_system", "nct_destroy_system", "nct_last_error", "nct_set_potentials",
               "nct_density_magnetization", "nct_apply_hamiltonian", "nct_step",
               "nct_backward_step", "nct_magnetization_seed", "nct_get_fields", "nct_version",
-              "nct_set_laser"]:
+              "nct_set_laser", "nct_set_laser_gauge", "nct_set_kpoints", "nct_dm_initialization",
+              "nct_ground_state", "nct_set_timing_sample"]:
         assert f in names
 
 
@@ -48,6 +49,7 @@ int main(void) {
          offsetof(nct_params, overlap), offsetof(nct_params, stream));
   printf("%zu %zu\n", offsetof(nct_pulse, e1), offsetof(nct_bfield, pulses));
   printf("%zu %zu\n", sizeof(nct_laser_pulse), offsetof(nct_laser_pulse, pol));
+  printf("%zu %zu\n", sizeof(nct_atom_density), offsetof(nct_atom_density, moment));
   return 0;
 }
 '''
@@ -65,6 +67,7 @@ int main(void) {
                           P.tape_steps.offset, P.overlap.offset, P.stream.offset]
     assert vals[11:13] == [nct.Pulse.e1.offset, nct.BField.pulses.offset]
     assert vals[13:15] == [ctypes.sizeof(nct.LaserPulse), nct.LaserPulse.pol.offset]
+    assert vals[15:17] == [ctypes.sizeof(nct.AtomDensity), nct.AtomDensity.moment.offset]
 
 
 def test_binding_refuses_without_gpu():

@@ -1,0 +1,123 @@
+"""Initial spin-density matrix (Sec. 3.2) and the imaginary-time ground state on the GPU against
+the oracle."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import nct_oracle as O
+from paper_2506_21908_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def _atoms(natoms):
+    moments = [(0.0, 0.0, 2.0), (1.5, 0.0, 0.5), (0.0, -1.0, 1.0), (0.5, 0.5, -1.5)]
+    return [O.AtomDensitySpec(Z=3.0 + 0.5 * a, sigma=0.8 + 0.1 * a, moment=moments[a % 4])
+            for a in range(natoms)]
+
+
+def test_dm_initialization_vs_oracle(torch_cuda):
+    torch = torch_cuda
+    from paper_2506_21908_amd import nct
+    say("DM initialisation 16x12x16, 3 atoms")
+    w = I.make_system(n=(16, 12, 16), L=(9.0, 7.0, 9.0), nstates=2, natoms=3, case=62, min_sep=2.5)
+    atoms = _atoms(3)
+    ref = O.dm_initialization(O.Grid(w.n, w.L), w.positions, atoms)
+    s = nct.system_from_workload(w)
+    rho = torch.empty((4,) + w.n, dtype=torch.float64, device="cuda")
+    s.dm_initialization(atoms, rho_v=rho, update_fields=True)
+    got = rho.cpu().numpy()
+    assert rel(got, ref) < 1e-13
+    # the fields now come from this density
+    sysd = O.system_from_workload(w)
+    F = O.fields_from_density(sysd, ref, 0.0)
+    out = torch.empty((4,) + w.n, dtype=torch.float64, device="cuda")
+    s.get_fields(0.0, out)
+    assert rel(out.cpu().numpy()[0], F.v) < 1e-12
+    assert rel(out.cpu().numpy()[1:], F.b) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_ground_state_vs_oracle(torch_cuda, prec):
+    """25 imaginary-time iterations (exchange, Hartree, SOC projectors, static B) starting from the
+    initial spin-density matrix: energies after every iteration and the final density."""
+    from paper_2506_21908_amd import nct
+    say(f"ground state {prec}")
+    w = I.make_system(n=(16, 16, 16), L=(8.0,) * 3, nstates=4, natoms=2, case=63, min_sep=3.0,
+                      bfield=I.BField(B0=(0.0, 0.0, 0.02)), full_spinors=True)
+    atoms = _atoms(2)
+    sysd = O.system_from_workload(w)
+    rho0 = O.dm_initialization(sysd.grid, w.positions, atoms)
+    # tau |H_max| = 0.03 x 59 Ha stays inside the stability range of T_4(-x) (x < 2.78)
+    psi_ref, E_ref = O.ground_state(sysd, w.psi0, 25, 0.03, rho_init=rho0)
+    pf = nct.NCT_FP64 if prec == "fp64" else nct.NCT_FP32_MIXED
+    s = nct.system_from_workload(w, precision=pf)
+    s.dm_initialization(atoms, update_fields=True)
+    psi = nct.states_to_device(w.psi0, pf)
+    E = s.ground_state(psi, 25, 0.03, keep_fields=True)
+    say(f"  E oracle {E_ref[0]:.12f} .. {E_ref[-1]:.12f}   gpu {E[0]:.12f} .. {E[-1]:.12f}")
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert np.max(np.abs(E - E_ref)) < tol * np.max(np.abs(E_ref))
+    na, ma = O.charge_and_magnetization(O.spin_density(psi.cpu().numpy().astype(np.complex128), sysd.occ))
+    nb, mb = O.charge_and_magnetization(O.spin_density(psi_ref, sysd.occ))
+    assert np.linalg.norm(na - nb) / np.linalg.norm(nb) < tol
+    assert np.linalg.norm(ma - mb) / np.linalg.norm(nb) < tol
+    assert E[-1] < E[0]
+
+
+def test_ground_state_cluster_runs_and_descends(torch_cuda):
+    """The 48^3 x 64 cluster: 20 iterations from the initial spin-density matrix; the energy falls
+    and the states stay orthonormal."""
+    torch = torch_cuda
+    from paper_2506_21908_amd import nct
+    w = I.workload(1)
+    say(f"{w.name}: 20 ground-state iterations")
+    s = nct.system_from_workload(w)
+    s.dm_initialization(_atoms(w.natoms), update_fields=True)
+    psi = nct.states_to_device(w.psi0)
+    t0 = time.time()
+    E = s.ground_state(psi, 20, 0.02, keep_fields=True)
+    torch.cuda.synchronize()
+    say(f"  {20 / (time.time() - t0):.1f} iterations/s, E {E[0]:.6f} -> {E[-1]:.6f}")
+    assert E[-1] < E[0]
+    f = psi.reshape(w.nstates, -1)
+    dV = float(np.prod(w.L)) / float(np.prod(w.n))
+    ovl = (f.conj() @ f.T * dV).cpu().numpy()
+    assert np.abs(ovl - np.eye(w.nstates)).max() < 1e-12
+
+
+def test_ground_state_argument_errors(torch_cuda):
+    from paper_2506_21908_amd import nct
+    w = I.make_system(n=(8, 8, 8), L=(6.0,) * 3, nstates=2, case=64)
+    s = nct.system_from_workload(w)
+    psi = nct.states_to_device(w.psi0)
+    with pytest.raises(nct.NctError) as e:
+        s.ground_state(psi, 3, -0.1)
+    assert e.value.code == nct.NCT_ERR_ARG
+    with pytest.raises(nct.NctError) as e:   # no atoms in this system
+        s.dm_initialization([O.AtomDensitySpec(1.0, 1.0)])
+    assert e.value.code == nct.NCT_ERR_ARG
+    dup = psi.clone()
+    dup[1] = dup[0]
+    with pytest.raises(nct.NctError) as e:   # linearly dependent states
+        s.ground_state(dup, 1, 0.03)
+    assert e.value.code == nct.NCT_ERR_NONFINITE
