@@ -936,6 +936,17 @@ struct Engine {
   // imaginary time: when > 0, taylor() forms T_K(-imag_tau H) x (real Horner coefficients)
   double imag_tau = 0.0;
 
+  // Horner coefficient of stage k: -i a/(K-k+1), or -imag_tau/(K-k+1) in imaginary time
+  void set_coeff(StageArgs<R>& sa, int k, int K, double a) const {
+    if (imag_tau > 0.0) {
+      sa.cre = R(-imag_tau / double(K - k + 1));
+      sa.cim = R(0);
+    } else {
+      sa.cre = R(0);
+      sa.cim = R(-a / double(K - k + 1));
+    }
+  }
+
   // T_K(-i a H) x by Horner stages w_k = x + (-i a/(K-k+1)) H w_{k-1}, w_0 = x.
   // stage_out[k-1] (k = 1..K-1), if given, receives w_k (the adjoint tape); else the work buffer.
   // kin_save: keep the first stage's column pass in this buffer; kin_reuse: take the first
@@ -966,13 +977,7 @@ struct Engine {
       sa.w_in = cw;
       sa.x_base = x;
       sa.alpha = R(1);
-      if (imag_tau > 0.0) {
-        sa.cre = R(-imag_tau / double(K - k + 1));
-        sa.cim = R(0);
-      } else {
-        sa.cre = R(0);
-        sa.cim = R(-a / double(K - k + 1));
-      }
+      set_coeff(sa, k, K, a);
       sa.w_out = last ? out : (stage_out ? stage_out[k - 1] : s->wbuf);
       sa.tmp_out = last ? outhat : s->tmp;
       sa.W = s->natoms ? (last ? outW : s->Wwork) : nullptr;

@@ -199,8 +199,35 @@ __host__ __device__ constexpr int plan_span(int N, int s) {
 }
 
 // ---------------------------------------------------------------- one LDS stage
+// Butterfly of stage STAGE on its RAD operands x (in place); b: index within the stage's block,
+// tw[e] = exp(-2 pi i e / N).  Forward (DIF): DFT then twiddles; inverse (DIT): conjugate
+// twiddles then DFT.
+template <typename R, int N, int STAGE, bool FWD>
+__device__ __forceinline__ void stage_butterfly(cpx<R>* x, const cpx<R>* tw, int b) {
+  constexpr int RAD = plan_radix(N, STAGE);
+  constexpr int SPAN = plan_span(N, STAGE);
+  constexpr int M = SPAN / RAD;
+  constexpr int TWS = N / SPAN;
+  if constexpr (M > 1) {
+    cpx<R> w[RAD - 1];
+#pragma unroll
+    for (int p = 1; p < RAD; ++p) w[p - 1] = tw[b * p * TWS];
+    if constexpr (FWD) {
+      dft<R, -1, RAD>(x);
+#pragma unroll
+      for (int p = 1; p < RAD; ++p) x[p] = cmul(x[p], w[p - 1]);
+    } else {
+#pragma unroll
+      for (int p = 1; p < RAD; ++p) x[p] = cmulc(x[p], w[p - 1]);
+      dft<R, +1, RAD>(x);
+    }
+  } else {
+    dft<R, FWD ? -1 : +1, RAD>(x);
+  }
+}
+
 // Lines of length N at lds + line*LS + k*ES.  Work item it -> (line = it % NLINES, butterfly),
-// so that neighbouring lanes work on neighbouring lines.  tw[e] = exp(-2 pi i e / N).
+// so that neighbouring lanes work on neighbouring lines.
 template <typename R, int N, int STAGE, int NLINES, int LS, int ES, bool FWD>
 __device__ __forceinline__ void lds_stage(cpx<R>* lds, const cpx<R>* tw, int tid, int nt) {
   constexpr int RAD = plan_radix(N, STAGE);
@@ -208,7 +235,6 @@ __device__ __forceinline__ void lds_stage(cpx<R>* lds, const cpx<R>* tw, int tid
   constexpr int M = SPAN / RAD;
   constexpr int NBF = N / RAD;
   constexpr int TOTAL = NLINES * NBF;
-  constexpr int TWS = N / SPAN;
   for (int it = tid; it < TOTAL; it += nt) {
     const int line = it % NLINES;
     const int bfi = it / NLINES;
@@ -218,25 +244,100 @@ __device__ __forceinline__ void lds_stage(cpx<R>* lds, const cpx<R>* tw, int tid
     cpx<R> x[RAD];
 #pragma unroll
     for (int q = 0; q < RAD; ++q) x[q] = base[q * M * ES];
-    if constexpr (M > 1) {
-      // all twiddle reads issued together with the data reads
-      cpx<R> w[RAD - 1];
-#pragma unroll
-      for (int p = 1; p < RAD; ++p) w[p - 1] = tw[b * p * TWS];
-      if constexpr (FWD) {
-        dft<R, -1, RAD>(x);
-#pragma unroll
-        for (int p = 1; p < RAD; ++p) x[p] = cmul(x[p], w[p - 1]);
-      } else {
-#pragma unroll
-        for (int p = 1; p < RAD; ++p) x[p] = cmulc(x[p], w[p - 1]);
-        dft<R, +1, RAD>(x);
-      }
-    } else {
-      dft<R, FWD ? -1 : +1, RAD>(x);
-    }
+    stage_butterfly<R, N, STAGE, FWD>(x, tw, b);
 #pragma unroll
     for (int q = 0; q < RAD; ++q) base[q * M * ES] = x[q];
+  }
+}
+
+// A stage whose operands come from memory through ld(g) instead of LDS (g = line*GLS + k*GES,
+// positions in an unpadded plane), results to LDS: the first stage of a transform fused with
+// the load of its input.  Every load of the thread is issued before its first butterfly; a
+// barrier precedes the butterflies (twiddles and earlier LDS writes visible) and follows the
+// LDS writes.
+template <typename R, int N, int STAGE, int NLINES, int LS, int ES, int GLS, int GES, int NT, bool FWD,
+          typename LD>
+__device__ __forceinline__ void stage_from(cpx<R>* lds, const cpx<R>* tw, int tid, LD ld) {
+  constexpr int RAD = plan_radix(N, STAGE);
+  constexpr int SPAN = plan_span(N, STAGE);
+  constexpr int M = SPAN / RAD;
+  constexpr int TOTAL = NLINES * (N / RAD);
+  constexpr int IT = (TOTAL + NT - 1) / NT;
+  cpx<R> x[IT][RAD];
+#pragma unroll
+  for (int u = 0; u < IT; ++u) {
+    const int it = tid + u * NT;
+    if ((u + 1) * NT <= TOTAL || it < TOTAL) {  // only a last, partial round has idle items
+      const int line = it % NLINES;
+      const int bfi = it / NLINES;
+      const int blk = bfi / M;
+      const int k0 = blk * SPAN + (bfi - blk * M);
+#pragma unroll
+      for (int q = 0; q < RAD; ++q) x[u][q] = ld(line * GLS + (k0 + q * M) * GES);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < IT; ++u) {
+    const int it = tid + u * NT;
+    if (it < TOTAL) {
+      const int line = it % NLINES;
+      const int bfi = it / NLINES;
+      const int blk = bfi / M;
+      const int b = bfi - blk * M;
+      stage_butterfly<R, N, STAGE, FWD>(x[u], tw, b);
+      cpx<R>* base = lds + line * LS + (blk * SPAN + b) * ES;
+#pragma unroll
+      for (int q = 0; q < RAD; ++q) base[q * M * ES] = x[u][q];
+    }
+  }
+  __syncthreads();
+}
+
+// A stage reading LDS whose results go to st(g, l, v, u) (g: unpadded position as above, l: the
+// LDS position, v: the value, u: what pre(g) returned for that position, loaded before the
+// butterflies) instead of back to LDS: the last stage of a transform fused with the store of its
+// output.  No barrier.
+template <typename R, int N, int STAGE, int NLINES, int LS, int ES, int GLS, int GES, int NT, bool FWD,
+          typename PRE, typename ST>
+__device__ __forceinline__ void stage_to(const cpx<R>* lds, const cpx<R>* tw, int tid, PRE pre, ST st) {
+  constexpr int RAD = plan_radix(N, STAGE);
+  constexpr int SPAN = plan_span(N, STAGE);
+  constexpr int M = SPAN / RAD;
+  constexpr int TOTAL = NLINES * (N / RAD);
+  constexpr int IT = (TOTAL + NT - 1) / NT;
+  using U = decltype(pre(0));
+  U u[IT][RAD];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int it = tid + k * NT;
+    if ((k + 1) * NT <= TOTAL || it < TOTAL) {
+      const int line = it % NLINES;
+      const int bfi = it / NLINES;
+      const int blk = bfi / M;
+      const int k0 = blk * SPAN + (bfi - blk * M);
+#pragma unroll
+      for (int q = 0; q < RAD; ++q) u[k][q] = pre(line * GLS + (k0 + q * M) * GES);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int it = tid + k * NT;
+    if (it < TOTAL) {
+      const int line = it % NLINES;
+      const int bfi = it / NLINES;
+      const int blk = bfi / M;
+      const int b = bfi - blk * M;
+      const int k0 = blk * SPAN + b;
+      const cpx<R>* base = lds + line * LS + k0 * ES;
+      cpx<R> x[RAD];
+#pragma unroll
+      for (int q = 0; q < RAD; ++q) x[q] = base[q * M * ES];
+      stage_butterfly<R, N, STAGE, FWD>(x, tw, b);
+#pragma unroll
+      for (int q = 0; q < RAD; ++q)
+        st(line * GLS + (k0 + q * M) * GES, line * LS + (k0 + q * M) * ES, x[q], u[k][q]);
+    }
   }
 }
 
@@ -284,6 +385,42 @@ __device__ __forceinline__ void plane_fft_inv(cpx<R>* lds, const cpx<R>* twy, co
                                               int tid, int nt) {
   lds_fft<R, NY, NZ, 1, PZ, false>(lds, twy, tid, nt);
   lds_fft<R, NZ, NY, PZ, 1, false>(lds, twz, tid, nt);
+}
+
+// Inverse 2D transform of a plane read through ld(y*NZ + z) (digit-reversed (y,z) order, as the
+// forward transform leaves it) into lds[y*PZ + z]: the first column stage is fused with the load.
+// No barrier is needed before the call; one follows it.
+template <typename R, int NY, int NZ, int PZ, int NT, typename LD>
+__device__ __forceinline__ void plane_fft_inv_from(cpx<R>* lds, const cpx<R>* twy, const cpx<R>* twz, int tid,
+                                                   LD ld) {
+  constexpr int NS = plan_nstages(NY);
+  stage_from<R, NY, NS - 1, NZ, 1, PZ, 1, NZ, NT, false>(lds, twy, tid, ld);
+  if constexpr (NS > 2) {
+    lds_stage<R, NY, 1, NZ, 1, PZ, false>(lds, twy, tid, NT);
+    __syncthreads();
+  }
+  if constexpr (NS > 1) {
+    lds_stage<R, NY, 0, NZ, 1, PZ, false>(lds, twy, tid, NT);
+    __syncthreads();
+  }
+  lds_fft<R, NZ, NY, PZ, 1, false>(lds, twz, tid, NT);
+}
+// Forward 2D transform of lds[y*PZ + z] whose output goes to st(y*NZ + z, y*PZ + z, value,
+// pre(y*NZ + z)): the last column stage is fused with the store.  Needs a barrier before the call; none follows it.
+template <typename R, int NY, int NZ, int PZ, int NT, typename PRE, typename ST>
+__device__ __forceinline__ void plane_fft_fwd_to(cpx<R>* lds, const cpx<R>* twy, const cpx<R>* twz, int tid,
+                                                 PRE pre, ST st) {
+  constexpr int NS = plan_nstages(NY);
+  lds_fft<R, NZ, NY, PZ, 1, true>(lds, twz, tid, NT);
+  if constexpr (NS > 1) {
+    lds_stage<R, NY, 0, NZ, 1, PZ, true>(lds, twy, tid, NT);
+    __syncthreads();
+  }
+  if constexpr (NS > 2) {
+    lds_stage<R, NY, 1, NZ, 1, PZ, true>(lds, twy, tid, NT);
+    __syncthreads();
+  }
+  stage_to<R, NY, NS - 1, NZ, 1, PZ, 1, NZ, NT, true>(lds, twy, tid, pre, st);
 }
 
 // Workgroup index remap so that consecutive logical indices run on one XCD.

@@ -316,20 +316,12 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(Stag
   const size_t offh = h ? off1 : off0;
   cpx<R>* pl = planes + h * PL;
 
-  // 1) kinetic part: each half loads and inverse-transforms its spinor's plane
+  // 1) kinetic part: each half loads and inverse-transforms its spinor's plane (the first
+  //    transform stage works on the loaded values)
   {
-    const cpx<R>* __restrict__ tin = reinterpret_cast<const cpx<R>*>(a.tmp_in);
-    cpx<R> v[PPH];
-#pragma unroll
-    for (int j = 0; j < PPH; ++j) v[j] = ld_stream<M>(&tin[offh + min(th + j * NTH, NP - 1)]);
-#pragma unroll
-    for (int j = 0; j < PPH; ++j) {
-      const int e = th + j * NTH;
-      if (e < NP) pl[(e / NZ) * PZ + (e % NZ)] = v[j];
-    }
+    const cpx<R>* __restrict__ tin = reinterpret_cast<const cpx<R>*>(a.tmp_in) + offh;
+    plane_fft_inv_from<R, NY, NZ, PZ, NTH>(pl, twy, twz, th, [&](int g) { return ld_stream<M>(&tin[g]); });
   }
-  __syncthreads();
-  plane_fft_inv<R, NY, NZ, PZ>(pl, twy, twz, th, NTH);
 
   // 2) 2x2 local potential and Taylor update over the whole plane (both spinors per point)
   {
@@ -453,12 +445,9 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(Stag
   }
   if (tout) {
     __syncthreads();
-    plane_fft_fwd<R, NY, NZ, PZ>(pl, twy, twz, th, NTH);
-#pragma unroll
-    for (int j = 0; j < PPH; ++j) {
-      const int e = th + j * NTH;
-      if (e < NP) st_stream<M>(&tout[offh + e], pl[(e / NZ) * PZ + (e % NZ)]);
-    }
+    cpx<R>* __restrict__ to = tout + offh;
+    plane_fft_fwd_to<R, NY, NZ, PZ, NTH>(pl, twy, twz, th, [](int) { return 0; },
+                                         [&](int g, int, cpx<R> v, int) { st_stream<M>(&to[g], v); });
   }
 }
 
@@ -591,34 +580,47 @@ _Pragma("clang loop unroll(full)")
         vy[j] = q.y;
       }
     }
-    lds_fft<R, NX, TC, 1, TC, true>(tile, tw, tid, XP_NT);
-_Pragma("clang loop unroll(full)")
-    for (int j = 0; j < PER; ++j) {
-      const int e = tid + j * XP_NT;
-      if (e < NX * TC) {
-        R g;
-        if (kt.kv) {  // |G + k|^2 of this spinor component's state
-          const R* k = kt.kv + 3 * (kt.state_off + b / 2);
-          const R gx = kt.gx[e / TC] + (k[0] + kt.ka[0]);
-          const R gy = kt.gy[q0 + (e % TC)] + (k[1] + kt.ka[1]);
-          const R gz = kt.gz[q0 + (e % TC)] + (k[2] + kt.ka[2]);
-          g = gx * gx + gy * gy + gz * gz;
-        } else {
-          g = g2x[e / TC] + g2yz[q0 + (e % TC)];
-        }
-        R m;
-        if (mode == 0) m = kscale * g;
-        else m = g > R(0) ? kscale / g : R(0);
-        tile[e] = cscale(tile[e], m);
-      }
+    // forward DFT along x; its last stage applies the kinetic (mode 0) or Poisson (mode 1)
+    // factor as it writes back; the inverse DFT's last stage stores to dst
+    constexpr int NS = plan_nstages(NX);
+    if constexpr (NS > 1) {
+      lds_stage<R, NX, 0, TC, 1, TC, true>(tile, tw, tid, XP_NT);
+      __syncthreads();
     }
+    if constexpr (NS > 2) {
+      lds_stage<R, NX, 1, TC, 1, TC, true>(tile, tw, tid, XP_NT);
+      __syncthreads();
+    }
+    stage_to<R, NX, NS - 1, TC, 1, TC, 1, TC, XP_NT, true>(
+        tile, tw, tid, [](int) { return 0; }, [&](int e, int l, cpx<R> v, int) {
+          R g;
+          if (kt.kv) {  // |G + k|^2 of this spinor component's state
+            const R* k = kt.kv + 3 * (kt.state_off + b / 2);
+            const R gx = kt.gx[e / TC] + (k[0] + kt.ka[0]);
+            const R gy = kt.gy[q0 + (e % TC)] + (k[1] + kt.ka[1]);
+            const R gz = kt.gz[q0 + (e % TC)] + (k[2] + kt.ka[2]);
+            g = gx * gx + gy * gy + gz * gz;
+          } else {
+            g = g2x[e / TC] + g2yz[q0 + (e % TC)];
+          }
+          R m;
+          if (mode == 0) m = kscale * g;
+          else m = g > R(0) ? kscale / g : R(0);
+          tile[l] = cscale(v, m);
+        });
     __syncthreads();
-    lds_fft<R, NX, TC, 1, TC, false>(tile, tw, tid, XP_NT);
-_Pragma("clang loop unroll(full)")
-    for (int j = 0; j < PER; ++j) {
-      const int e = tid + j * XP_NT;
-      if (e < NX * TC) st_stream<M>(&dst[bbase + size_t(q0) + size_t(e / TC) * NYZ + (e % TC)], tile[e]);
+    if constexpr (NS > 2) {
+      lds_stage<R, NX, 2, TC, 1, TC, false>(tile, tw, tid, XP_NT);
+      __syncthreads();
     }
+    if constexpr (NS > 1) {
+      lds_stage<R, NX, 1, TC, 1, TC, false>(tile, tw, tid, XP_NT);
+      __syncthreads();
+    }
+    stage_to<R, NX, 0, TC, 1, TC, 1, TC, XP_NT, false>(
+        tile, tw, tid, [](int) { return 0; }, [&](int e, int, cpx<R> v, int) {
+          st_stream<M>(&dst[bbase + size_t(q0) + size_t(e / TC) * NYZ + (e % TC)], v);
+        });
     __syncthreads();
   }
 }
