@@ -274,9 +274,13 @@ template <int NY, int NZ>
 constexpr size_t plane2_lds_bytes(size_t elem) {
   return (size_t(2) * NY * (NZ + 1) + NY + NZ) * elem;
 }
+// LDS budget of the two-plane kernel (tuning macro; 160 KiB per CU less a margin)
+#ifndef NCT_PLANE2_MAX_LDS
+#define NCT_PLANE2_MAX_LDS (160 * 1024 - 1024)
+#endif
 template <typename R, int NY, int NZ>
 constexpr bool plane2_fits() {
-  return plane2_lds_bytes<NY, NZ>(sizeof(cpx<R>)) <= 160 * 1024 - 1024;
+  return plane2_lds_bytes<NY, NZ>(sizeof(cpx<R>)) <= NCT_PLANE2_MAX_LDS;
 }
 
 template <typename R, int NY, int NZ, int M>
@@ -536,55 +540,31 @@ constexpr int xpass_tc(int nx) {
 }
 constexpr int XP_NT = 256;
 
-// Column pass over XP_T consecutive tiles per workgroup: the loads of tile t+1 are issued
-// before tile t is transformed, so each workgroup keeps global loads in flight during its LDS
-// work.  Tile = TC consecutive yz columns x NX planes of one batch entry (spinor component).
-// XT tiles per workgroup (XT divides the tile count; compile time, so the loop unrolls).
-template <typename R, int NX, int TC, int XT, int M>
+// Column pass: one workgroup per tile of TC consecutive yz columns x NX planes of one batch
+// entry (spinor component).  The first forward x stage works on the values as they are loaded.
+template <typename R, int NX, int TC, int M>
 __global__ __launch_bounds__(XP_NT) void k_xpass(const cpx<R>* src, cpx<R>* dst, int NYZ,
                                                  const R* __restrict__ g2x,
                                                  const R* __restrict__ g2yz, R kscale, int mode,
                                                  const cpx<R>* __restrict__ twx_g, KTables<R> kt) {
   __shared__ cpx<R> tile[NX * TC];
   __shared__ cpx<R> tw[NX];
-  constexpr int PER = (NX * TC + XP_NT - 1) / XP_NT;
   const int tid = threadIdx.x;
-  const int groups = NYZ / (TC * XT);
-  const int b = blockIdx.x / groups;
-  const int t0 = (blockIdx.x - b * groups) * XT;
+  const int tiles = NYZ / TC;
+  const int b = blockIdx.x / tiles;
+  const int q0 = (blockIdx.x - b * tiles) * TC;
   for (int k = tid; k < NX; k += XP_NT) tw[k] = twx_g[k];
-  const size_t bbase = size_t(b) * NX * NYZ;
-  R vx[PER], vy[PER];  // prefetch registers (separate real/imag arrays stay in VGPRs)
-_Pragma("clang loop unroll(full)")
-  for (int j = 0; j < PER; ++j) {
-    const int e = min(tid + j * XP_NT, NX * TC - 1);
-    const cpx<R> q = ld_stream<M>(&src[bbase + size_t(t0) * TC + size_t(e / TC) * NYZ + (e % TC)]);
-    vx[j] = q.x;
-    vy[j] = q.y;
-  }
-_Pragma("clang loop unroll(full)")
-  for (int u = 0; u < XT; ++u) {
-    const int q0 = (t0 + u) * TC;
-_Pragma("clang loop unroll(full)")
-    for (int j = 0; j < PER; ++j) {
-      const int e = tid + j * XP_NT;
-      if (e < NX * TC) tile[e] = cpx<R>{vx[j], vy[j]};
-    }
-    __syncthreads();
-    if (u + 1 < XT) {  // prefetch the next tile while this one is transformed
-_Pragma("clang loop unroll(full)")
-      for (int j = 0; j < PER; ++j) {
-        const int e = min(tid + j * XP_NT, NX * TC - 1);
-        const cpx<R> q = ld_stream<M>(&src[bbase + size_t(q0 + TC) + size_t(e / TC) * NYZ + (e % TC)]);
-        vx[j] = q.x;
-        vy[j] = q.y;
-      }
-    }
+  const cpx<R>* srcb = src + size_t(b) * NX * NYZ + q0;
+  cpx<R>* dstb = dst + size_t(b) * NX * NYZ + q0;
+  {
     // forward DFT along x; its last stage applies the kinetic (mode 0) or Poisson (mode 1)
     // factor as it writes back; the inverse DFT's last stage stores to dst
     constexpr int NS = plan_nstages(NX);
     if constexpr (NS > 1) {
-      lds_stage<R, NX, 0, TC, 1, TC, true>(tile, tw, tid, XP_NT);
+      stage_from<R, NX, 0, TC, 1, TC, 1, TC, XP_NT, true>(
+          tile, tw, tid, [&](int e) { return ld_stream<M>(&srcb[size_t(e / TC) * NYZ + (e % TC)]); });
+    } else {
+      for (int e = tid; e < NX * TC; e += XP_NT) tile[e] = ld_stream<M>(&srcb[size_t(e / TC) * NYZ + (e % TC)]);
       __syncthreads();
     }
     if constexpr (NS > 2) {
@@ -619,9 +599,8 @@ _Pragma("clang loop unroll(full)")
     }
     stage_to<R, NX, 0, TC, 1, TC, 1, TC, XP_NT, false>(
         tile, tw, tid, [](int) { return 0; }, [&](int e, int, cpx<R> v, int) {
-          st_stream<M>(&dst[bbase + size_t(q0) + size_t(e / TC) * NYZ + (e % TC)], v);
+          st_stream<M>(&dstb[size_t(e / TC) * NYZ + (e % TC)], v);
         });
-    __syncthreads();
   }
 }
 
@@ -1469,15 +1448,15 @@ static hipError_t launch_xpass_tc(int B, int NYZ, const void* src, void* dst, co
   const auto s_ = reinterpret_cast<const cpx<R>*>(src);
   const auto d_ = reinterpret_cast<cpx<R>*>(dst);
   const auto t_ = reinterpret_cast<const cpx<R>*>(twx);
-  // one tile per workgroup: prefetching a second tile (XT > 1) measured no faster on MI355X and
-  // costs occupancy
+  // one tile per workgroup (a second, prefetched tile per workgroup measured no faster on
+  // MI355X and costs occupancy)
   const dim3 grid(unsigned(B) * unsigned(tiles));
   if (cache_mode >= 2)
-    nct_launch((k_xpass<R, NX, TC, 1, 2>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_, kt);
+    nct_launch((k_xpass<R, NX, TC, 2>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_, kt);
   else if (cache_mode == 1)
-    nct_launch((k_xpass<R, NX, TC, 1, 1>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_, kt);
+    nct_launch((k_xpass<R, NX, TC, 1>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_, kt);
   else
-    nct_launch((k_xpass<R, NX, TC, 1, 0>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_, kt);
+    nct_launch((k_xpass<R, NX, TC, 0>), grid, dim3(XP_NT), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_, kt);
   return hipGetLastError();
 }
 
