@@ -112,7 +112,7 @@ typedef struct {
   const nct_channel *channels;/* host [nchannels], the same table for every atom */
   double r_sphere;            /* projector sphere radius (bohr), < half the smallest cell edge */
   int xc;                     /* 0: none; 1: Slater exchange; 2: Slater exchange + PW92 correlation
-                                 (LSDA); both locally collinear.  nct_backward_step needs xc <= 1 */
+                                 (LSDA); both locally collinear */
   int hartree;                /* 0: none; 1: FFT Poisson */
   double m_threshold;         /* |m| below which b_xc = 0 (bohr^-3) */
   double dt;                  /* time step (a.u.) */
@@ -259,15 +259,16 @@ nct_status nct_magnetization_seed(nct_system *sys, const void *psi_dev, const do
 
 /* Reverse-mode (adjoint) of one ETRS step n -> n+1.  With lam = 2 dL/dpsi* (so that
  * dL = Re sum lam^* dpsi), given lam_{n+1} returns lam_n, including the response of the
- * Hartree and exchange fields to the density at psi_n and psi~.  The forward quantities come
+ * Hartree and exchange(-correlation) fields to the density at psi_n and psi~.  The forward quantities come
  * from tape record tape_index of the last taped nct_step, or, when tape_index < 0, are
  * recomputed from psi_n_dev (device, psi layout) at time t_n.
  *   dLdB_host      host double[6]: dL/dB_ext(t_n) (3) and dL/dB_ext(t_n + dt) (3);
  *   dLdtheta_host  host double[2*npulses]: dL/d(A_k) then dL/d(omega_k) are ADDED to it
  *                  (accumulate over steps), or NULL.
- * lam_np1_dev and lam_n_dev may be the same buffer.  With self-consistent fields the adjoint
- * covers xc <= 1 (NCT_ERR_UNSUPPORTED for xc = 2).  A laser (nct_set_laser) is re-applied in
- * the reverse stages at the forward times. */
+ * lam_np1_dev and lam_n_dev may be the same buffer.  Every xc setting is covered (the PW92
+ * correlation response by forward-mode derivatives of its potentials).  A laser (nct_set_laser)
+ * is re-applied in the reverse stages at the forward times; the velocity gauge is not covered
+ * (NCT_ERR_UNSUPPORTED). */
 nct_status nct_backward_step(nct_system *sys, int tape_index, const void *psi_n_dev, double t_n,
                              const void *lam_np1_dev, void *lam_n_dev, double *dLdB_host,
                              double *dLdtheta_host);

@@ -183,12 +183,23 @@ def pw92_G(rs, par):
     return q0 * lg, -2.0 * A * a1 * lg - q0 * q1p / (q1 * q1 + q1)
 
 
+def _cbrt(x):
+    """Real cube root; for the complex-step derivative (complex x near the positive real axis)
+    the principal root, with a zero imaginary part where the real part is 0 (the derivative of
+    the clamped channel is taken as 0 there)."""
+    if not np.iscomplexobj(x):
+        return np.cbrt(x)
+    r = np.where(x.real > 0, x, 1.0) ** (1.0 / 3.0)
+    return np.where(x.real > 0, r, 0.0)
+
+
 def pw92_f(zeta):
     """Spin interpolation f(zeta) = [(1+z)^(4/3) + (1-z)^(4/3) - 2] / (2^(4/3) - 2) and f'."""
     d = 2.0 ** (4.0 / 3.0) - 2.0
     up, dn = 1.0 + zeta, 1.0 - zeta
-    f = (up ** (4.0 / 3.0) + dn ** (4.0 / 3.0) - 2.0) / d
-    fp = (4.0 / 3.0) * (np.cbrt(up) - np.cbrt(dn)) / d
+    f = (up * _cbrt(up) + dn * _cbrt(dn) - 2.0) / d if np.iscomplexobj(zeta) else \
+        (up ** (4.0 / 3.0) + dn ** (4.0 / 3.0) - 2.0) / d
+    fp = (4.0 / 3.0) * (_cbrt(up) - _cbrt(dn)) / d
     return f, fp
 
 
@@ -227,6 +238,37 @@ def pw92_correlation(n: np.ndarray, m: np.ndarray, thr: float = 1e-12):
     bc = np.where(big, dz / safe_mu, 0.0) * m
     ec = np.where(ok, n * eps, 0.0)
     return vbar, bc, ec
+
+
+def pw92_correlation_jvp(n, m, dn, dm, thr: float = 1e-12):
+    """Directional derivative of (vbar_c, b_c) of pw92_correlation along (dn, dm).
+
+    In (n, |m|) the potentials are vbar_c(n, mu) and bmag_c(n, mu) = d eps/d zeta; their
+    derivatives along (dn, dmu), dmu = mhat.dm, come from one complex-step evaluation
+    (Squire & Trapp, SIAM Rev. 40, 110 (1998)): d f = Im f(n + i h dn, mu + i h dmu) / h,
+    exact to rounding for these analytic formulas; the clamp of zeta to [0, 1] acts on the real
+    part.  d b_c = d bmag mhat + bmag d mhat, as for exchange; b_c = 0 where |m| < thr (and there
+    dmu = 0)."""
+    mu = np.sqrt(m[0] ** 2 + m[1] ** 2 + m[2] ** 2)
+    big = mu >= thr
+    safe_mu = np.where(big, mu, 1.0)
+    mhat = np.where(big, 1.0, 0.0) * m / safe_mu
+    dmu = np.sum(mhat * dm, axis=0)
+    ok = n > PW92_NMIN
+    scale = max(float(np.max(np.abs(dn))), float(np.max(np.abs(dmu))), 1e-300)
+    h = 1e-20 / scale
+    nc = np.where(ok, n, 1.0) + 1j * h * np.where(ok, dn, 0.0)
+    muc = mu + 1j * h * dmu
+    rs = _cbrt(3.0 / (4.0 * math.pi * nc))
+    zr = (muc / nc).real
+    zeta = np.where(zr < 0.0, 0.0, np.where(zr > 1.0, 1.0, muc / nc))
+    eps, drs, dz = pw92_eps(rs, zeta)
+    vbar = eps - rs / 3.0 * drs - zeta * dz
+    dvbar = np.where(ok, vbar.imag / h, 0.0)
+    dbmag = np.where(ok & big, dz.imag / h, 0.0)
+    bmag = np.where(ok & big, dz.real, 0.0)
+    dmhat = np.where(big, 1.0, 0.0) * (dm - mhat * dmu) / safe_mu
+    return dvbar, dbmag * mhat + bmag * dmhat
 
 
 def slater_exchange_jvp(n, m, dn, dm, thr: float = 1e-12):
@@ -766,13 +808,14 @@ def _density_jvp(psi, dpsi, occ):
 
 
 def _fields_jvp(sysd: System, rho_v, drho_v, dB):
-    if sysd.xc >= 2:
-        raise NotImplementedError("tangent-linear fields cover exchange only (xc <= 1)")
     n, m = charge_and_magnetization(rho_v)
     dn, dm = charge_and_magnetization(drho_v)
     dvH = hartree(dn, sysd.grid) if sysd.hartree else np.zeros_like(n)
     if sysd.xc:
         dvbar, dbxc = slater_exchange_jvp(n, m, dn, dm, sysd.thr)
+        if sysd.xc >= 2:
+            dvc, dbc = pw92_correlation_jvp(n, m, dn, dm, sysd.thr)
+            dvbar, dbxc = dvbar + dvc, dbxc + dbc
     else:
         dvbar, dbxc = np.zeros_like(n), np.zeros_like(m)
     return dvH + dvbar, dbxc + MU_B * np.asarray(dB)[:, None, None, None]

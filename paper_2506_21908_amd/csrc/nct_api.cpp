@@ -1919,8 +1919,6 @@ nct_status nct_backward_step(nct_system* s, int tape_index, const void* psi_n, d
   if (!s) return NCT_ERR_ARG;
   if (!lam_np1 || !lam_n) return fail(s, NCT_ERR_ARG, "lam_np1 / lam_n is NULL");
   if (s->frozen && !s->fields_valid) return fail(s, NCT_ERR_STATE, "no fields");
-  if (s->prm.xc >= 2 && !s->frozen)
-    return fail(s, NCT_ERR_UNSUPPORTED, "the adjoint step covers exchange only (xc <= 1)");
   if (velocity_gauge(s))
     return fail(s, NCT_ERR_UNSUPPORTED, "the adjoint step does not cover the velocity-gauge laser");
   nct_system::Tape* T = nullptr;

@@ -691,44 +691,87 @@ __global__ __launch_bounds__(256) void k_density(const cpx<R>* __restrict__ psi,
 //   n_s = (n +/- |m|)/2, v_s = -(6/pi)^(1/3) n_s^(1/3), vbar = (v_up+v_dn)/2,
 //   b_xc = (v_up - v_dn)/2 m/|m| (0 below threshold), e_x = -(3/4)(6/pi)^(1/3) sum n_s^(4/3).
 // v_up - v_dn is evaluated as -(6/pi)^(1/3) (n_up - n_dn) / (n_up^(2/3) + (n_up n_dn)^(1/3) + n_dn^(2/3)).
+// Dual number v + d e (e^2 = 0) for forward-mode derivatives of the correlation potentials in
+// the adjoint; the elementary functions below take double or dual.  cbrt's derivative at 0 is
+// taken as 0 (the one-sided value of the clamped channel).
+struct dnum {
+  double v, d;
+};
+__device__ __forceinline__ dnum operator+(dnum a, dnum b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ dnum operator-(dnum a, dnum b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ dnum operator*(dnum a, dnum b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ dnum operator/(dnum a, dnum b) {
+  return {a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)};
+}
+__device__ __forceinline__ dnum operator+(double a, dnum b) { return {a + b.v, b.d}; }
+__device__ __forceinline__ dnum operator+(dnum a, double b) { return {a.v + b, a.d}; }
+__device__ __forceinline__ dnum operator-(double a, dnum b) { return {a - b.v, -b.d}; }
+__device__ __forceinline__ dnum operator-(dnum a, double b) { return {a.v - b, a.d}; }
+__device__ __forceinline__ dnum operator*(double a, dnum b) { return {a * b.v, a * b.d}; }
+__device__ __forceinline__ dnum operator*(dnum a, double b) { return {a.v * b, a.d * b}; }
+__device__ __forceinline__ dnum operator/(double a, dnum b) { return {a / b.v, -a * b.d / (b.v * b.v)}; }
+__device__ __forceinline__ dnum operator/(dnum a, double b) { return {a.v / b, a.d / b}; }
+__device__ __forceinline__ double xval(double x) { return x; }
+__device__ __forceinline__ double xval(dnum x) { return x.v; }
+__device__ __forceinline__ double xcbrt(double x) { return cbrt(x); }
+__device__ __forceinline__ dnum xcbrt(dnum x) {
+  const double c = cbrt(x.v);
+  return {c, c != 0.0 ? x.d / (3.0 * c * c) : 0.0};
+}
+__device__ __forceinline__ double xsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ dnum xsqrt(dnum x) {
+  const double r = sqrt(x.v);
+  return {r, x.d / (2.0 * r)};
+}
+__device__ __forceinline__ double xlog1p(double x) { return log1p(x); }
+__device__ __forceinline__ dnum xlog1p(dnum x) { return {log1p(x.v), x.d / (1.0 + x.v)}; }
+__device__ __forceinline__ double xclamp01(double x) { return fmin(fmax(x, 0.0), 1.0); }
+__device__ __forceinline__ dnum xclamp01(dnum x) {
+  if (x.v < 0.0) return {0.0, 0.0};
+  if (x.v > 1.0) return {1.0, 0.0};
+  return x;
+}
+
 // PW92 LSDA correlation (J. P. Perdew and Y. Wang, Phys. Rev. B 45, 13244 (1992)).
 // G(rs) = -2A(1 + a1 rs) ln[1 + 1/(2A(b1 rs^1/2 + b2 rs + b3 rs^3/2 + b4 rs^2))] and dG/drs.
-__device__ __forceinline__ void pw92_g(double rs, double srs, double A, double a1, double b1,
-                                       double b2, double b3, double b4, double& g, double& dg) {
-  const double q0 = -2.0 * A * (1.0 + a1 * rs);
-  const double q1 = 2.0 * A * (b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs);
-  const double q1p = A * (b1 / srs + 2.0 * b2 + 3.0 * b3 * srs + 4.0 * b4 * rs);
-  const double lg = log1p(1.0 / q1);
+template <typename T>
+__device__ __forceinline__ void pw92_g(T rs, T srs, double A, double a1, double b1, double b2, double b3,
+                                       double b4, T& g, T& dg) {
+  const T q0 = -2.0 * A * (1.0 + a1 * rs);
+  const T q1 = 2.0 * A * (b1 * srs + b2 * rs + b3 * rs * srs + b4 * rs * rs);
+  const T q1p = A * (b1 / srs + 2.0 * b2 + 3.0 * b3 * srs + 4.0 * b4 * rs);
+  const T lg = xlog1p(1.0 / q1);
   g = q0 * lg;
   dg = -2.0 * A * a1 * lg - q0 * q1p / (q1 * q1 + q1);
 }
 // Locally collinear PW92 at density n and |m| = mu: vbar = (v_up + v_dn)/2, bmag = (v_up - v_dn)/2
-// (the field along m/|m|), ec = n eps_c; zero where n <= 1e-30.
-__device__ void pw92_lc(double n, double mu, double& vbar, double& bmag, double& ec) {
-  vbar = bmag = ec = 0.0;
-  if (!(n > 1e-30)) return;
-  const double rs = cbrt(0.75 / (3.14159265358979323846 * n));
-  const double srs = sqrt(rs);
-  const double z = fmin(fmax(mu / n, 0.0), 1.0);
-  double e0, d0, e1, d1, ma, dma;
+// (the field along m/|m|), ec = n eps_c; zero where n <= 1e-30.  T = dnum carries the derivative
+// along the direction given in n.d, mu.d; T = double is the plain evaluation.
+template <typename T>
+__device__ void pw92_lc(T n, T mu, T& vbar, T& bmag, T& ec) {
+  vbar = bmag = ec = T{};
+  if (!(xval(n) > 1e-30)) return;
+  const T rs = xcbrt(0.75 / (3.14159265358979323846 * n));
+  const T srs = xsqrt(rs);
+  const T z = xclamp01(mu / n);
+  T e0, d0, e1, d1, ma, dma;
   pw92_g(rs, srs, 0.031091, 0.21370, 7.5957, 3.5876, 1.6382, 0.49294, e0, d0);    // zeta = 0
   pw92_g(rs, srs, 0.015545, 0.20548, 14.1189, 6.1977, 3.3662, 0.62517, e1, d1);   // zeta = 1
   pw92_g(rs, srs, 0.016887, 0.11125, 10.357, 3.6231, 0.88026, 0.49671, ma, dma);  // -alpha_c
-  const double ac = -ma, dac = -dma;
+  const T ac = 0.0 - ma, dac = 0.0 - dma;
   const double fpp0 = 1.709921;
   const double fden = 0.5198420997897464;  // 2^(4/3) - 2
-  const double cu = cbrt(1.0 + z), cd = cbrt(1.0 - z);
-  const double f = ((1.0 + z) * cu + (1.0 - z) * cd - 2.0) / fden;
-  const double fp = (4.0 / 3.0) * (cu - cd) / fden;
-  const double z3 = z * z * z, z4 = z3 * z;
-  const double eps = e0 + ac * f * (1.0 - z4) / fpp0 + (e1 - e0) * f * z4;
-  const double drs = d0 * (1.0 - f * z4) + d1 * f * z4 + dac * f * (1.0 - z4) / fpp0;
-  const double dz = 4.0 * z3 * f * (e1 - e0 - ac / fpp0) + fp * (z4 * (e1 - e0) + (1.0 - z4) * ac / fpp0);
+  const T cu = xcbrt(1.0 + z), cd = xcbrt(1.0 - z);
+  const T f = ((1.0 + z) * cu + (1.0 - z) * cd - 2.0) / fden;
+  const T fp = (4.0 / 3.0) * (cu - cd) / fden;
+  const T z3 = z * z * z, z4 = z3 * z;
+  const T eps = e0 + ac * f * (1.0 - z4) / fpp0 + (e1 - e0) * f * z4;
+  const T drs = d0 * (1.0 - f * z4) + d1 * f * z4 + dac * f * (1.0 - z4) / fpp0;
+  const T dz = 4.0 * z3 * f * (e1 - e0 - ac / fpp0) + fp * (z4 * (e1 - e0) + (1.0 - z4) * ac / fpp0);
   vbar = eps - rs / 3.0 * drs - z * dz;
   bmag = dz;
   ec = n * eps;
 }
-
 __global__ __launch_bounds__(256) void k_fields(const double* __restrict__ rho,
                                                 const double* __restrict__ vext,
                                                 const double* __restrict__ vH, int xc, double thr,
@@ -763,7 +806,7 @@ __global__ __launch_bounds__(256) void k_fields(const double* __restrict__ rho,
       }
       if (xc >= 2) {
         double vc, bc, ec;
-        pw92_lc(n, mu, vc, bc, ec);
+        pw92_lc<double>(n, mu, vc, bc, ec);
         vbar += vc;
         ex += ec;
         if (mu >= thr) bmag += bc;
@@ -1074,24 +1117,42 @@ __global__ __launch_bounds__(256) void k_field_adjoint(const double* __restrict_
     double gn = pg ? pg[p] : 0.0;
     double gmx = 0, gmy = 0, gmz = 0;
     if (xc) {
+      // v = vbar(n, |m|), b = bmag(n, |m|) m/|m| (|m| >= thr); with J the Jacobian of
+      // (vbar, bmag) in (n, |m|) and g_r = mhat.g_b:
+      //   g_n += J00 g_v + J10 g_r,  g_m = (J01 g_v + J11 g_r) mhat + (bmag/|m|)(g_b - mhat g_r)
       const double c = 1.2407009817988000;  // (6/pi)^(1/3)
       const double ruu = rho[p], rdd = rho[N + p], rr = rho[2 * N + p], ri = rho[3 * N + p];
       const double n = ruu + rdd, mx = 2.0 * rr, my = -2.0 * ri, mz = ruu - rdd;
       const double mu = sqrt(mx * mx + my * my + mz * mz);
       const double nu = 0.5 * (n + mu), nd = 0.5 * (n - mu);
       const double cu = nu > 0 ? cbrt(nu) : 0.0, cd = nd > 0 ? cbrt(nd) : 0.0;
+      // exchange: v_s depends on n_s alone, dv_s/dn_s = du, dd
       const double du = nu > 0 ? -(c / 3.0) / (cu * cu) : 0.0;
       const double dd = nd > 0 ? -(c / 3.0) / (cd * cd) : 0.0;
-      gn += 0.25 * (du + dd) * gv;
+      double j00 = 0.25 * (du + dd), j01 = 0.25 * (du - dd), j10 = j01, j11 = j00;
+      double bmag = 0.0;
+      if (mu >= thr) {
+        const double nuc = fmax(nu, 0.0), ndc = fmax(nd, 0.0);
+        const double den = cu * cu + cu * cd + cd * cd;
+        bmag = den > 0.0 ? -0.5 * c * (nuc - ndc) / den : 0.0;
+      }
+      if (xc >= 2) {  // PW92 correlation: its Jacobian from two dual evaluations
+        dnum vb, bm, ec;
+        pw92_lc<dnum>(dnum{n, 1.0}, dnum{mu, 0.0}, vb, bm, ec);
+        j00 += vb.d;
+        j10 += bm.d;
+        pw92_lc<dnum>(dnum{n, 0.0}, dnum{mu, 1.0}, vb, bm, ec);
+        j01 += vb.d;
+        j11 += bm.d;
+        if (mu >= thr) bmag += bm.v;
+      }
+      gn += j00 * gv;
       if (mu >= thr) {
         const double hx = mx / mu, hy = my / mu, hz = mz / mu;
         const double mg = hx * gbx + hy * gby + hz * gbz;
-        const double nuc = fmax(nu, 0.0), ndc = fmax(nd, 0.0);
-        const double den = cu * cu + cu * cd + cd * cd;
-        const double bmag = den > 0.0 ? -0.5 * c * (nuc - ndc) / den : 0.0;
         const double bom = bmag / mu;
-        gn += 0.25 * (du - dd) * mg;
-        const double radial = 0.25 * (du - dd) * gv + 0.25 * (du + dd) * mg;
+        gn += j10 * mg;
+        const double radial = j01 * gv + j11 * mg;
         gmx = radial * hx + bom * (gbx - hx * mg);
         gmy = radial * hy + bom * (gby - hy * mg);
         gmz = radial * hz + bom * (gbz - hz * mg);

@@ -33,16 +33,17 @@ def _inner(a, b):
     return float(np.real(np.vdot(a, b)))
 
 
-@pytest.mark.parametrize("frozen", [False, True])
-def test_backward_step_dot_product(torch_cuda, frozen):
+@pytest.mark.parametrize("frozen,xc", [(False, 1), (True, 1), (False, 2)])
+def test_backward_step_dot_product(torch_cuda, frozen, xc):
     """Re<lam_n, dpsi_n> = Re<lam_{n+1}, J dpsi_n>, with J the oracle's tangent-linear step,
-    and dL/dB(t_n), dL/dB(t_n+dt) against the oracle's response to dB."""
+    and dL/dB(t_n), dL/dB(t_n+dt) against the oracle's response to dB (xc = 2: with the PW92
+    correlation response)."""
     torch = torch_cuda
     from paper_2506_21908_amd import nct
-    say(f"backward dot product frozen={frozen}")
+    say(f"backward dot product frozen={frozen} xc={xc}")
     bf = I.BField(B0=(0.01, 0.0, 0.02), pulses=I.circular_pulses([0.1], [0.7], 0.05, 0.2))
     w = I.make_system(n=(12, 12, 12), L=(7.0,) * 3, nstates=4, natoms=1, case=40, bfield=bf,
-                      full_spinors=False)
+                      full_spinors=False, xc=xc)
     sysd = O.system_from_workload(w)
     t_n = 0.1
     lam1 = _rand_states(w.psi0.shape, 1)
@@ -85,16 +86,17 @@ def test_backward_step_dot_product(torch_cuda, frozen):
     assert np.array_equal(dLdB, dLdB2)
 
 
-def test_pulse_gradient_vs_oracle_tangent_linear(torch_cuda):
+@pytest.mark.parametrize("xc", [1, 2])
+def test_pulse_gradient_vs_oracle_tangent_linear(torch_cuda, xc):
     """dM_z(T)/d(A_k, omega_k) through the checkpointed adjoint equals the oracle's forward-mode
-    gradient of the same discrete trajectory."""
+    gradient of the same discrete trajectory (xc = 2: LSDA)."""
     torch = torch_cuda
     from paper_2506_21908_amd import nct
-    say("pulse gradient vs oracle tangent-linear, 12^3 x 4, 8 steps")
+    say(f"pulse gradient vs oracle tangent-linear, 12^3 x 4, 8 steps, xc={xc}")
     pulses = I.circular_pulses([0.1, 0.25], [0.5, 1.0], 0.05, 0.15)
     bf = I.BField(pulses=pulses)
     w = I.make_system(n=(12, 12, 12), L=(7.0,) * 3, nstates=4, natoms=1, case=41, bfield=bf,
-                      full_spinors=False)
+                      full_spinors=False, xc=xc)
     sysd = O.system_from_workload(w)
     nsteps = 8
     g_ref = O.mz_gradient_tangent_linear(sysd, w.psi0, nsteps)

@@ -97,16 +97,3 @@ def test_lsda_cluster_workload_one_step_vs_oracle(torch_cuda):
     errs = _errors(obs, obs_ref[1:], psi.cpu().numpy(), psi_ref, sysd.occ)
     say("  N_e %.2e M %.2e E %.2e n %.2e m %.2e" % errs)
     assert max(errs) < 1e-10
-
-
-def test_lsda_adjoint_refused(torch_cuda):
-    torch = torch_cuda
-    from paper_2506_21908_amd import nct
-    w = I.make_system(n=(8, 8, 8), L=(6.0,) * 3, nstates=2, case=47, xc=2)
-    s = nct.system_from_workload(w, tape_steps=1)
-    psi = nct.states_to_device(w.psi0)
-    s.step(psi, 0.0, 1, tape=True)
-    lam = torch.zeros_like(psi)
-    with pytest.raises(nct.NctError) as e:
-        s.backward_step(0, None, 0.0, lam, lam)
-    assert e.value.code == nct.NCT_ERR_UNSUPPORTED

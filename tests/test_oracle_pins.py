@@ -861,7 +861,82 @@ def test_ground_state_self_consistent_with_exchange_and_hartree():
     assert abs(E[-1] - E[-2]) < 1e-12
 
 
+def test_pw92_jvp_matches_central_differences():
+    """The complex-step tangent of the correlation potentials equals central differences of
+    pw92_correlation (a different method), including strongly polarised points."""
+    rng = np.random.default_rng(5)
+    n = 10.0 ** rng.uniform(-4, 0.5, 40)
+    m = rng.standard_normal((3, 40))
+    m *= (rng.uniform(0.0, 0.97, 40) * n / np.sqrt(np.sum(m * m, axis=0)))
+    dn = rng.standard_normal(40) * n
+    dm = rng.standard_normal((3, 40)) * n
+    h = 1e-6
+    vp, bp, _ = O.pw92_correlation(n + h * dn, m + h * dm)
+    vm, bm, _ = O.pw92_correlation(n - h * dn, m - h * dm)
+    dv, db = O.pw92_correlation_jvp(n, m, dn, dm)
+    fv, fb = (vp - vm) / (2 * h), (bp - bm) / (2 * h)
+    assert np.all(np.abs(dv - fv) <= 1e-6 * np.abs(fv) + 1e-9)
+    assert np.all(np.abs(db - fb) <= 1e-6 * np.abs(fb) + 1e-9)
+
+
+def test_pw92_potentials_have_a_symmetric_jacobian():
+    """vbar_c = dE/dn and bmag_c = dE/d|m| are derivatives of one energy density, so
+    d vbar/d|m| = d bmag/dn: the tangent along |m| of vbar equals the tangent along n of
+    bmag (m along z, so that b_c = bmag e_z)."""
+    rng = np.random.default_rng(6)
+    n = rng.uniform(0.01, 2.0, 25)
+    mz = rng.uniform(0.05, 0.9, 25) * n
+    m = np.stack([np.zeros(25), np.zeros(25), mz])
+    one, zero = np.ones(25), np.zeros(25)
+    dv_mu, _ = O.pw92_correlation_jvp(n, m, zero, np.stack([zero, zero, one]))
+    _, db_n = O.pw92_correlation_jvp(n, m, one, np.zeros((3, 25)))
+    assert np.allclose(dv_mu, db_n[2], rtol=1e-11, atol=1e-14)
+
+
+def test_lsda_fields_jvp_matches_central_differences():
+    """Tangent of the self-consistent fields (Hartree + exchange + PW92 correlation) along a
+    density perturbation, against central differences of the fields themselves."""
+    w = I.make_system(n=(6, 6, 6), L=(6.0,) * 3, nstates=3, natoms=0, case=62, xc=2)
+    sysd = O.system_from_workload(w)
+    rho = O.spin_density(w.psi0, sysd.occ)
+    rng = np.random.default_rng(7)
+    dpsi = rng.standard_normal(w.psi0.shape) + 1j * rng.standard_normal(w.psi0.shape)
+    drho = O._density_jvp(w.psi0, dpsi, sysd.occ)
+    dv, db = O._fields_jvp(sysd, rho, drho, np.zeros(3))
+    h = 1e-6
+    Fp = O.fields_from_density(sysd, rho + h * drho, 0.0)
+    Fm = O.fields_from_density(sysd, rho - h * drho, 0.0)
+    fv, fb = (Fp.v - Fm.v) / (2 * h), (Fp.b - Fm.b) / (2 * h)
+    assert np.abs(dv - fv).max() < 1e-7 * np.abs(fv).max()
+    assert np.abs(db - fb).max() < 1e-7 * np.abs(fb).max()
+
+
 # ---------------------------------------------------------------- gradient oracle
+def test_tangent_linear_gradient_lsda_matches_central_differences():
+    """With PW92 correlation in the self-consistent fields (xc = 2), the forward-mode pulse
+    gradient of the discrete trajectory equals central differences of it."""
+    bf = I.BField(pulses=I.circular_pulses([0.1, 0.2], [0.5, 1.0], 0.05, 0.1))
+    w = I.make_system(n=(6, 6, 6), L=(6.0,) * 3, nstates=2, natoms=1, case=11, bfield=bf, dt=0.05,
+                      xc=2)
+    sysd = O.system_from_workload(w)
+    nsteps = 4
+    g = O.mz_gradient_tangent_linear(sysd, w.psi0, nsteps)
+    h = 1e-5
+    for k in (0, 3):
+        vals = []
+        for sgn in (1, -1):
+            pulses = [O.PulseSpec(**vars(p)) for p in sysd.bfield.pulses]
+            if k < 2:
+                pulses[k].A += sgn * h
+            else:
+                pulses[k - 2].omega += sgn * h
+            s2 = O.System(**{**vars(sysd), "bfield": O.FieldSpec(sysd.bfield.B0, pulses)})
+            psi, _ = O.run(s2, w.psi0, nsteps, record=False)
+            vals.append(O.total_mz(s2, psi))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[k]) < 1e-7 * max(1.0, abs(g[k])) + 1e-9, (k, fd, g[k])
+
+
 def test_tangent_linear_gradient_matches_central_differences():
     bf = I.BField(pulses=I.circular_pulses([0.1, 0.2], [0.5, 1.0], 0.05, 0.1))
     w = I.make_system(n=(6, 6, 6), L=(6.0,) * 3, nstates=2, natoms=1, case=11, bfield=bf, dt=0.05)
