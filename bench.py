@@ -221,7 +221,7 @@ def main():
         out["fp32_mixed"] = {"value": args.steps / el2, "unit": "steps/s",
                              "ms_per_step": 1e3 * el2 / args.steps,
                              "plane_stage_GBps": (by2 / (ms2 * 1e-3) / 1e9) if ms2 > 0 else None}
-    if not args.no_adjoint and not (w.laser and w.laser_gauge == "velocity"):
+    if not args.no_adjoint:
         C = args.adjoint_segment
         s = nct.system_from_workload(w, precision=pflag, tape_steps=C)
         psi = nct.states_to_device(w.psi0, pflag)

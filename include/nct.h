@@ -199,7 +199,7 @@ nct_status nct_ground_state(nct_system *sys, void *psi_dev, int niter, double ta
  *   NCT_GAUGE_VELOCITY: for periodic systems; every state's kinetic momentum is shifted by the
  *     vector potential A(t) = -int_0^t E dt' (evaluated like B_ext: t_n for H_n, t_n + dt for
  *     H~): kinetic factor 1/2 |G + k + A|^2 and projector phases exp(+/- i (k + A).d), no scalar
- *     potential and no E.D term in E_loc.  nct_backward_step refuses it (NCT_ERR_UNSUPPORTED).
+ *     potential and no E.D term in E_loc.
  * Errors: NCT_ERR_ARG for any other value. */
 enum { NCT_GAUGE_LENGTH = 0, NCT_GAUGE_VELOCITY = 1 };
 nct_status nct_set_laser_gauge(nct_system *sys, int gauge);
@@ -267,8 +267,7 @@ nct_status nct_magnetization_seed(nct_system *sys, const void *psi_dev, const do
  *                  (accumulate over steps), or NULL.
  * lam_np1_dev and lam_n_dev may be the same buffer.  Every xc setting is covered (the PW92
  * correlation response by forward-mode derivatives of its potentials).  A laser (nct_set_laser)
- * is re-applied in the reverse stages at the forward times; the velocity gauge is not covered
- * (NCT_ERR_UNSUPPORTED). */
+ * is re-applied in the reverse stages at the forward times, in either gauge. */
 nct_status nct_backward_step(nct_system *sys, int tape_index, const void *psi_n_dev, double t_n,
                              const void *lam_np1_dev, void *lam_n_dev, double *dLdB_host,
                              double *dLdtheta_host);

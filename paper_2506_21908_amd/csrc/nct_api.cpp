@@ -1169,12 +1169,12 @@ struct Engine {
              return launch_axpby<R>(acc, lam_out, cnt, R(1), R(0), R(1), s->st); }), "axpby")) != NCT_OK)
         return r;
     }
-    if ((r = prepare(lam_out, s->tmp, s->Wwork)) != NCT_OK) return r;
     StageArgs<R> sa;
     sa.cache_mode = s->cache_mode;
     sa.kv = kvR();
-    externals(t, sa);
+    externals(t, sa);  // first: the rows gathered below carry the Bloch phases at time t
     sa.fields = fieldsR();
+    if ((r = prepare(lam_out, s->tmp, s->Wwork)) != NCT_OK) return r;
     const void* cur = lam_out;
     for (int k = K; k >= 1; --k) {
       const double gamma = a / double(K - k + 1);
@@ -1919,8 +1919,6 @@ nct_status nct_backward_step(nct_system* s, int tape_index, const void* psi_n, d
   if (!s) return NCT_ERR_ARG;
   if (!lam_np1 || !lam_n) return fail(s, NCT_ERR_ARG, "lam_np1 / lam_n is NULL");
   if (s->frozen && !s->fields_valid) return fail(s, NCT_ERR_STATE, "no fields");
-  if (velocity_gauge(s))
-    return fail(s, NCT_ERR_UNSUPPORTED, "the adjoint step does not cover the velocity-gauge laser");
   nct_system::Tape* T = nullptr;
   int idx = 0;
   nct_status r;

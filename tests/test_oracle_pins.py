@@ -937,6 +937,35 @@ def test_tangent_linear_gradient_lsda_matches_central_differences():
         assert abs(fd - g[k]) < 1e-7 * max(1.0, abs(g[k])) + 1e-9, (k, fd, g[k])
 
 
+def test_tangent_linear_gradient_velocity_gauge_matches_central_differences():
+    """Periodic system with two k-points under a velocity-gauge laser: the forward-mode B-pulse
+    gradient of the discrete trajectory equals central differences of it."""
+    bf = I.BField(pulses=I.circular_pulses([0.1, 0.2], [0.5, 1.0], 0.05, 0.1))
+    laser = [I.LaserPulse(A=0.5, omega=0.4, t0=0.1, tau=0.4, phase=0.3, pol=(0.2, -0.3, 0.93))]
+    w = I.make_system(n=(6, 6, 6), L=(6.0,) * 3, nstates=2, natoms=1, case=11, bfield=bf, dt=0.05,
+                      laser=laser, full_spinors=True)
+    w.laser_gauge = "velocity"
+    w.kvec = np.array([[0.0, 0.0, 0.0], [0.3, -0.2, 0.1]])
+    w.occ = np.full(2, 0.5)
+    sysd = O.system_from_workload(w)
+    nsteps = 4
+    g = O.mz_gradient_tangent_linear(sysd, w.psi0, nsteps)
+    h = 1e-5
+    for k in (1, 2):
+        vals = []
+        for sgn in (1, -1):
+            pulses = [O.PulseSpec(**vars(p)) for p in sysd.bfield.pulses]
+            if k < 2:
+                pulses[k].A += sgn * h
+            else:
+                pulses[k - 2].omega += sgn * h
+            s2 = O.System(**{**vars(sysd), "bfield": O.FieldSpec(sysd.bfield.B0, pulses)})
+            psi, _ = O.run(s2, w.psi0, nsteps, record=False)
+            vals.append(O.total_mz(s2, psi))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g[k]) < 1e-7 * max(1.0, abs(g[k])) + 1e-9, (k, fd, g[k])
+
+
 def test_tangent_linear_gradient_matches_central_differences():
     bf = I.BField(pulses=I.circular_pulses([0.1, 0.2], [0.5, 1.0], 0.05, 0.1))
     w = I.make_system(n=(6, 6, 6), L=(6.0,) * 3, nstates=2, natoms=1, case=11, bfield=bf, dt=0.05)
