@@ -530,12 +530,20 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_inv(const cpx<R>* in
 }
 
 // ---------------------------------------------------------------- column pass along x
+// widest column-pass tile (64, 32, 16 columns) whose LDS footprint stays within a budget
+// (tuning macros, bytes per workgroup)
+#ifndef NCT_XPASS_TILE_MAX_F64
+#define NCT_XPASS_TILE_MAX_F64 32768
+#endif
+#ifndef NCT_XPASS_TILE_MAX_F32
+#define NCT_XPASS_TILE_MAX_F32 32768
+#endif
 template <typename R>
 constexpr int xpass_tc(int nx) {
-  // widest tile (64, 32, 16 columns) whose LDS footprint stays within 32 KiB
   const int b = int(sizeof(R)) * 2;
-  if (nx * 64 * b <= 32768) return 64;
-  if (nx * 32 * b <= 32768) return 32;
+  const int cap = sizeof(R) == 8 ? NCT_XPASS_TILE_MAX_F64 : NCT_XPASS_TILE_MAX_F32;
+  if (nx * 64 * b <= cap) return 64;
+  if (nx * 32 * b <= cap) return 32;
   return 16;
 }
 constexpr int XP_NT = 256;
