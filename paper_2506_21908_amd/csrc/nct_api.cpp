@@ -49,6 +49,10 @@ struct nct_system {
   hipStream_t st2 = nullptr;       // projector chain, overlapped with the column pass
   hipEvent_t ev_rows = nullptr;    // sphere rows ready (recorded on st)
   hipEvent_t ev_proj = nullptr;    // scatter rows ready (recorded on st2)
+  // stream of the early kinetic pass: the next step's first column pass runs there while the
+  // density and fields of the new states are formed on st
+  hipStream_t stK = nullptr;
+  hipEvent_t evK_in = nullptr, evK_out = nullptr;
   // second state group: its Taylor stages run on their own streams, overlapping the first
   // group's (states are contiguous in the state-major layout, so a group is a sub-array)
   int ngroups = 1;
@@ -126,6 +130,7 @@ struct nct_system {
   void* Wphi = nullptr;
   void* Wwork = nullptr;
   void* Y = nullptr;
+  void* Yphi = nullptr;       // scatter rows of phi's first stage, shared by the 2nd and 3rd exponentials
   void* Cpart = nullptr;
   void* C = nullptr;
   void* EC = nullptr;
@@ -512,6 +517,7 @@ nct_status build_projectors(nct_system* s) {
   if ((r = dalloc(s, rows, &s->Wphi)) != NCT_OK) return r;
   if ((r = dalloc(s, rows, &s->Wwork)) != NCT_OK) return r;
   if ((r = dalloc(s, rows, &s->Y)) != NCT_OK) return r;
+  if ((r = dalloc(s, rows, &s->Yphi)) != NCT_OK) return r;
   const size_t cp = size_t(s->natoms) * PP * s->S;
   if ((r = dalloc(s, cp * pt.max_kchunks * 16, &s->Cpart)) != NCT_OK) return r;
   if ((r = dalloc(s, cp * 16, &s->C)) != NCT_OK) return r;
@@ -882,10 +888,11 @@ struct Engine {
   // kin_dst: column-pass output buffer (default s->tmp); chat == nullptr: skip the column pass,
   // sa_full.tmp_in already holds it.
   nct_status stage_group(const Group& g, const void* cW, const void* chat, const StageArgs<R>& sa_full,
-                         void* kin_dst = nullptr) {
+                         void* kin_dst = nullptr, void* y_dst = nullptr, const void* y_src = nullptr) {
     nct_status r;
     const double frac = double(g.S) / double(s->S);
-    if (s->natoms) {
+    void* ybuf = y_dst ? y_dst : s->Y;
+    if (s->natoms && !y_src) {
       HIPCHK(s, hipEventRecord(g.ev_rows, g.st));
       HIPCHK(s, hipStreamWaitEvent(g.st2, g.ev_rows, 0));
       const double cpB = double(s->natoms) * s->pt.PP * g.S * 16.0;
@@ -896,7 +903,7 @@ struct Engine {
         return r;
       const double ecB = double(s->natoms) * s->pt.PP * g.S * sizeof(R) * 2;
       if ((r = check(timed_on(s, g.st2, NCT_K_PROJ, beta_bytes() + ecB + frac * rowsB(), frac * proj_flops(), [&] {
-                       return launch_proj_scatter<R>(s->pt, g.EC, g.S, offr(s->Y, g.i0), g.st2); }),
+                       return launch_proj_scatter<R>(s->pt, g.EC, g.S, offr(ybuf, g.i0), g.st2); }),
                      "proj_scatter")) != NCT_OK)
         return r;
       HIPCHK(s, hipEventRecord(g.ev_proj, g.st2));
@@ -908,7 +915,7 @@ struct Engine {
                                     R(0.5 / double(s->N)), 0, twx(), g.st, s->cache_mode, ktab(g.i0)); }), "xpass")) != NCT_OK)
         return r;
     }
-    if (s->natoms) HIPCHK(s, hipStreamWaitEvent(g.st, g.ev_proj, 0));
+    if (s->natoms && !y_src) HIPCHK(s, hipStreamWaitEvent(g.st, g.ev_proj, 0));
     StageArgs<R> sa = sa_full;
     sa.tmp_in = offs(sa.tmp_in, g.i0);
     sa.tmp_out = offs(sa.tmp_out, g.i0);
@@ -916,7 +923,7 @@ struct Engine {
     sa.x_base = offs(sa.x_base, g.i0);
     sa.w_out = offs(sa.w_out, g.i0);
     sa.acc = offs(sa.acc, g.i0);
-    sa.Y = s->natoms ? offr(s->Y, g.i0) : nullptr;
+    sa.Y = s->natoms ? offr(y_src ? y_src : ybuf, g.i0) : nullptr;
     sa.W = offr(sa.W, g.i0);
     sa.state_off = g.i0;
     double b = psiB();
@@ -951,9 +958,11 @@ struct Engine {
   // stage_out[k-1] (k = 1..K-1), if given, receives w_k (the adjoint tape); else the work buffer.
   // kin_save: keep the first stage's column pass in this buffer; kin_reuse: take the first
   // stage's column pass from this buffer instead of recomputing it (same x, fields-independent).
+  // y_save / y_reuse: the same for the first stage's projector scatter rows (they depend on x
+  // and the Bloch phases only).
   nct_status taylor(const void* x, const void* xhat, const void* xW, void* out, void* outhat,
                     void* outW, double t, void* const* stage_out = nullptr, void* kin_save = nullptr,
-                    const void* kin_reuse = nullptr) {
+                    const void* kin_reuse = nullptr, void* y_save = nullptr, const void* y_reuse = nullptr) {
     const int K = s->prm.taylor_order;
     const double a = 0.5 * s->prm.dt;
     const void* cw = x;
@@ -983,14 +992,30 @@ struct Engine {
       sa.W = s->natoms ? (last ? outW : s->Wwork) : nullptr;
       sa.acc = nullptr;
       for (int gi = 0; gi < ng; ++gi)
-        if ((r = stage_group(G[gi], cW, (first && kin_reuse) ? nullptr : chat, sa,
-                             first ? kin_save : nullptr)) != NCT_OK)
+        if ((r = stage_group(G[gi], cW, (first && kin_reuse) ? nullptr : chat, sa, first ? kin_save : nullptr,
+                             first ? y_save : nullptr, first ? y_reuse : nullptr)) != NCT_OK)
           return r;
       cw = sa.w_out;
       chat = sa.tmp_out;
       cW = sa.W;
     }
     return join_groups();
+  }
+
+  // The next step's first column pass (kinetic part for psi^ at time t) into s->tmp on stK, so
+  // that it overlaps the density and field update that follow on st; that step's first Taylor
+  // stage takes it as kin_reuse after waiting for evK_out.
+  nct_status early_kinetic(double t) {
+    at_time(t);
+    HIPCHK(s, hipEventRecord(s->evK_in, s->st));
+    HIPCHK(s, hipStreamWaitEvent(s->stK, s->evK_in, 0));
+    nct_status r = check(timed_on(s, s->stK, NCT_K_XPASS, 2 * psiB(), 0, [&] {
+                           return launch_xpass<R>(s->n, 2 * s->S, s->psihat, s->tmp, g2x(), g2yz(),
+                                                  R(0.5 / double(s->N)), 0, twx(), s->stK, s->cache_mode,
+                                                  ktab()); }), "xpass");
+    if (r != NCT_OK) return r;
+    HIPCHK(s, hipEventRecord(s->evK_out, s->stK));
+    return NCT_OK;
   }
 
   nct_status prepare(const void* psi, void* hat, void* W) {
@@ -1069,6 +1094,7 @@ struct Engine {
     }
     at_time(t0);
     if ((r = prepare(cur, s->psihat, s->Wpsi)) != NCT_OK) return r;
+    if (nsteps > 0 && (r = early_kinetic(t0)) != NCT_OK) return r;
     if (!s->frozen) {
       if ((r = density(cur)) != NCT_OK) return r;
       if ((r = fields_from_rho(true)) != NCT_OK) return r;
@@ -1096,13 +1122,17 @@ struct Engine {
         ptil = tvec(*T, k, 3 * K - 1);
         next = (k + 1 < nsteps) ? tvec(*T, k + 1, 0) : psi;
       }
-      if ((r = taylor(cur, s->psihat, s->Wpsi, phi, s->phihat, s->Wphi, t, T ? so1.data() : nullptr)) != NCT_OK)
+      // the first column pass ran early on stK (early_kinetic)
+      HIPCHK(s, hipStreamWaitEvent(s->st, s->evK_out, 0));
+      if ((r = taylor(cur, s->psihat, s->Wpsi, phi, s->phihat, s->Wphi, t, T ? so1.data() : nullptr, nullptr,
+                      s->tmp)) != NCT_OK)
         return r;
-      // the second and third exponentials share phi's kinetic column pass unless the kinetic
-      // term itself depends on time (velocity-gauge laser)
+      // the second and third exponentials share phi's kinetic column pass and first scatter rows
+      // unless the kinetic term and the projector phases depend on time (velocity-gauge laser)
       const bool vg = velocity_gauge(s);
+      void* yphi = (vg || !s->natoms) ? nullptr : s->Yphi;
       if ((r = taylor(phi, s->phihat, s->Wphi, ptil, nullptr, nullptr, t, T ? so2.data() : nullptr,
-                      vg ? nullptr : s->tmpk_phi)) != NCT_OK)
+                      vg ? nullptr : s->tmpk_phi, nullptr, yphi)) != NCT_OK)
         return r;
       if (!s->frozen) {
         if ((r = density(ptil)) != NCT_OK) return r;
@@ -1118,9 +1148,10 @@ struct Engine {
           return r;
       }
       if ((r = taylor(phi, s->phihat, s->Wphi, next, s->psihat, s->Wpsi, t + dt, T ? so3.data() : nullptr,
-                      nullptr, vg ? nullptr : s->tmpk_phi)) != NCT_OK)
+                      nullptr, vg ? nullptr : s->tmpk_phi, nullptr, yphi)) != NCT_OK)
         return r;
       cur = next;
+      if (k + 1 < nsteps && (r = early_kinetic(t + dt)) != NCT_OK) return r;
       if (!s->frozen || obs_host) {
         if ((r = density(cur)) != NCT_OK) return r;
         if ((r = fields_from_rho(!s->frozen)) != NCT_OK) return r;
@@ -1508,11 +1539,12 @@ void free_all(nct_system* s) {
   }
   for (auto& b : s->owned) (void)hipFree(b.p);
   s->owned.clear();
-  for (hipEvent_t* e : {&s->ev_rows, &s->ev_proj, &s->evB_rows, &s->evB_proj, &s->ev_fork, &s->ev_join}) {
+  for (hipEvent_t* e : {&s->ev_rows, &s->ev_proj, &s->evB_rows, &s->evB_proj, &s->ev_fork, &s->ev_join,
+                        &s->evK_in, &s->evK_out}) {
     if (*e) (void)hipEventDestroy(*e);
     *e = nullptr;
   }
-  for (hipStream_t* q : {&s->st2, &s->stB, &s->stB2}) {
+  for (hipStream_t* q : {&s->st2, &s->stB, &s->stB2, &s->stK}) {
     if (*q) {
       (void)hipStreamSynchronize(*q);
       (void)hipStreamDestroy(*q);
@@ -1643,8 +1675,11 @@ nct_status create_impl(const nct_params* p, nct_system** out) {
   s->gtot = (double*)p0;
   if (p->tape_steps > 0 && (r = alloc_tape(s, s->tape, p->tape_steps)) != NCT_OK) return bail(r);
   if (hipStreamCreateWithFlags(&s->st2, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&s->stK, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&s->ev_rows, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess ||
-      hipEventCreateWithFlags(&s->ev_proj, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess) {
+      hipEventCreateWithFlags(&s->ev_proj, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess ||
+      hipEventCreateWithFlags(&s->evK_in, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess ||
+      hipEventCreateWithFlags(&s->evK_out, hipEventDisableTiming | hipEventDisableSystemFence) != hipSuccess) {
     fail(s, NCT_ERR_HIP, "stream/event creation failed");
     return bail(NCT_ERR_HIP);
   }
