@@ -96,7 +96,6 @@ struct nct_system {
   // device: fields and densities (FP64)
   double* occ = nullptr;
   double* vext = nullptr;
-  double* vH = nullptr;
   double* rho = nullptr;
   double* fields = nullptr;    // [4][N] v, b_xc (no B_ext)
   double* fields_scr = nullptr;
@@ -152,7 +151,6 @@ struct nct_system {
   double* gA = nullptr;       // [4][N] field gradients
   double* gB = nullptr;
   double* gnm = nullptr;      // [4][N] density gradients
-  double* pg = nullptr;       // [N] Poisson of g_v
   double* gpart = nullptr;    // [nblk][4]
   double* gtot = nullptr;     // [4]
 
@@ -731,11 +729,9 @@ struct Engine {
     const double N = double(s->N);
     const int K = NCT_K_FIELDS;
     if (s->prm.hartree) {
-      if ((r = check(timed(s, K, 32 * N, 0, [&] { return launch_rho_to_n(s->rho, s->N, s->ncpx, s->st); }),
-                     "rho_to_n")) != NCT_OK) return r;
       if ((r = check(timed(s, K, 32 * N, 0, [&] {
-             return launch_plane_fwd<double>(s->n, 1, s->ncpx, s->ncpx, nullptr, nullptr, s->tw64[1],
-                                             s->tw64[2], s->st); }), "poisson fwd")) != NCT_OK) return r;
+             return launch_plane_fwd_real(s->n, s->rho, 1, s->ncpx, s->tw64[1], s->tw64[2], s->st); }),
+                     "poisson fwd")) != NCT_OK) return r;
       if ((r = check(timed(s, K, 32 * N, 0, [&] {
              return launch_xpass<double>(s->n, 1, s->ncpx, s->ncpx, s->g2x64, s->g2yz64,
                                          4.0 * kPi / double(s->N), 1, s->tw64[0], s->st); }),
@@ -743,9 +739,7 @@ struct Engine {
       if ((r = check(timed(s, K, 32 * N, 0, [&] {
              return launch_plane_inv<double>(s->n, 1, s->ncpx, s->ncpx, 1.0, s->tw64[1], s->tw64[2],
                                              s->st); }), "poisson inv")) != NCT_OK) return r;
-      if ((r = check(timed(s, K, 24 * N, 0, [&] { return launch_cpx_real(s->ncpx, s->N, s->vH, s->st); }),
-                     "cpx_real")) != NCT_OK) return r;
-      vh = s->vH;
+      vh = reinterpret_cast<const double*>(s->ncpx);  // v_H: the real parts
     }
     int nb = 0;
     double* out = store ? s->fields : s->fields_scr;
@@ -1238,11 +1232,9 @@ struct Engine {
     const double N = double(s->N);
     const double* pgp = nullptr;
     if (s->prm.hartree) {
-      if ((r = check(timed(s, NCT_K_ADJOINT, 24 * N, 0, [&] { return launch_real_to_cpx(g, s->N, s->ncpx, s->st); }),
-                     "real_to_cpx")) != NCT_OK) return r;
-      if ((r = check(timed(s, NCT_K_ADJOINT, 32 * N, 0, [&] {
-             return launch_plane_fwd<double>(s->n, 1, s->ncpx, s->ncpx, nullptr, nullptr, s->tw64[1],
-                                             s->tw64[2], s->st); }), "adj poisson fwd")) != NCT_OK) return r;
+      if ((r = check(timed(s, NCT_K_ADJOINT, 24 * N, 0, [&] {
+             return launch_plane_fwd_real(s->n, g, 2, s->ncpx, s->tw64[1], s->tw64[2], s->st); }),
+                     "adj poisson fwd")) != NCT_OK) return r;
       if ((r = check(timed(s, NCT_K_ADJOINT, 32 * N, 0, [&] {
              return launch_xpass<double>(s->n, 1, s->ncpx, s->ncpx, s->g2x64, s->g2yz64,
                                          4.0 * kPi / double(s->N), 1, s->tw64[0], s->st); }),
@@ -1250,9 +1242,7 @@ struct Engine {
       if ((r = check(timed(s, NCT_K_ADJOINT, 32 * N, 0, [&] {
              return launch_plane_inv<double>(s->n, 1, s->ncpx, s->ncpx, 1.0, s->tw64[1], s->tw64[2],
                                              s->st); }), "adj poisson inv")) != NCT_OK) return r;
-      if ((r = check(timed(s, NCT_K_ADJOINT, 24 * N, 0, [&] { return launch_cpx_real(s->ncpx, s->N, s->pg, s->st); }),
-                     "adj cpx_real")) != NCT_OK) return r;
-      pgp = s->pg;
+      pgp = reinterpret_cast<const double*>(s->ncpx);  // the real parts
     }
     int nb = 0;
     if ((r = check(timed(s, NCT_K_ADJOINT, 96 * N, 0, [&] {
@@ -1633,8 +1623,6 @@ nct_status create_impl(const nct_params* p, nct_system** out) {
   const size_t N = s->N;
   if ((r = dalloc(s, N * 8, &p0)) != NCT_OK) return bail(r);
   s->vext = (double*)p0;
-  if ((r = dalloc(s, N * 8, &p0)) != NCT_OK) return bail(r);
-  s->vH = (double*)p0;
   if ((r = dalloc(s, 4 * N * 8, &p0)) != NCT_OK) return bail(r);
   s->rho = (double*)p0;
   if ((r = dalloc(s, 4 * N * 8, &p0)) != NCT_OK) return bail(r);
@@ -1667,8 +1655,6 @@ nct_status create_impl(const nct_params* p, nct_system** out) {
   s->gB = (double*)p0;
   if ((r = dalloc(s, 4 * N * 8, &p0)) != NCT_OK) return bail(r);
   s->gnm = (double*)p0;
-  if ((r = dalloc(s, N * 8, &p0)) != NCT_OK) return bail(r);
-  s->pg = (double*)p0;
   if ((r = dalloc(s, ((N + 255) / 256) * 4 * 8, &p0)) != NCT_OK) return bail(r);
   s->gpart = (double*)p0;
   if ((r = dalloc(s, 4 * 8, &p0)) != NCT_OK) return bail(r);

@@ -76,6 +76,10 @@ hipError_t launch_plane_stage(const int n[3], int S, const StageArgs<R>& a, cons
 // sphere rows of the input into W (batch must then be 2S in state/spinor order).
 // With kt.kv (Bloch vectors [S][3], shifted by kt.ka) the gathered rows carry exp(i k.d) (state
 // of entry b = b / 2).
+// forward (y,z) transform of a real source (B = 1): src 1 = spin density [4][N] (n = rho_uu +
+// rho_dd), 2 = real array [N]; out: complex [N]
+hipError_t launch_plane_fwd_real(const int n[3], const double* in, int src, void* out, const void* twy,
+                                 const void* twz, hipStream_t st);
 template <typename R>
 hipError_t launch_plane_fwd(const int n[3], int B, const void* in, void* out, void* W,
                             const ProjTables* pt, const void* twy, const void* twz, hipStream_t st,
@@ -113,13 +117,12 @@ hipError_t launch_density(const void* psi, const double* occ, int S, size_t N, d
 constexpr int kFieldTot = 12;  // N_e, M_x, M_y, M_z, E_loc, E_H, E_xc, 0, D_x, D_y, D_z, 0
 // D = sum (r - c) n, r = (ix hx, iy hy, iz hz), c = cell / 2: the dipole that gives the laser
 // energy E.D dV.
+// vH: the complex Poisson output (its real parts, stride 2 doubles, are v_H), or null
 hipError_t launch_fields(const double* rho, const double* vext, const double* vH, int xc,
                          double thr, const int n[3], const double cell[3], double* fields,
                          float* fields32, double* part, int* nblk_out, hipStream_t st);
 hipError_t launch_reduce_rows(const double* part, int nrows, int width, double* out,
                               hipStream_t st);
-hipError_t launch_rho_to_n(const double* rho, size_t N, void* ncpx, hipStream_t st);
-hipError_t launch_cpx_real(const void* c, size_t N, double* out, hipStream_t st);
 // out = fields + {v_E, b}: v_E = lg[0] ix + lg[1] iy + lg[2] iz + lg[3] (laser), b added to b_xc
 hipError_t launch_add_bext(const double* fields, const int n[3], const double b[3],
                            const double lg[4], double* out, hipStream_t st);
@@ -159,13 +162,13 @@ hipError_t launch_axpby(void* y, const void* x, size_t count, R a_re, R a_im, R 
 template <typename R>
 hipError_t launch_pair(const void* mu, const void* w, int S, size_t N, double gamma, double* g,
                        hipStream_t st);
+// pg: the complex adjoint Poisson output (its real parts, stride 2 doubles, are used), or null
 hipError_t launch_field_adjoint(const double* rho, const double* g, const double* pg, int xc,
                                 double thr, size_t N, double* gnm, double* part, int* nblk_out,
                                 hipStream_t st);
 template <typename R>
 hipError_t launch_density_backprop(const void* psi, const double* occ, const double* gnm, int S,
                                    size_t N, int add, void* lam, hipStream_t st);
-hipError_t launch_real_to_cpx(const double* r, size_t N, void* out, hipStream_t st);
 
 // HIP events attached to the next kernel dispatches of this host thread (set by the library's
 // timing wrapper around one launcher call): 'start' goes with the first dispatch and 'stop' with

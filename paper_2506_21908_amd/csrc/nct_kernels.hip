@@ -456,7 +456,9 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(Stag
 }
 
 // ---------------------------------------------------------------- plane pass: transform only
-template <typename R, int NY, int NZ>
+// SRC: what `in` holds: 0 complex values; 1 a spin density rho_v (real, [4][N]; the transform
+// takes n = rho_uu + rho_dd), 2 a real array (the transform takes it as the real part).
+template <typename R, int NY, int NZ, int SRC = 0>
 __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_fwd(const cpx<R>* in, cpx<R>* out,
                                                                  cpx<R>* W, ProjTables pt,
                                                                  const cpx<R>* __restrict__ twy_g,
@@ -476,7 +478,14 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_fwd(const cpx<R>* in
   for (int k = tid; k < NY; k += NT) twy[k] = twy_g[k];
   for (int k = tid; k < NZ; k += NT) twz[k] = twz_g[k];
   const size_t off = (size_t(b) * NX + x) * NP;
-  for (int e = tid; e < NP; e += NT) plane[(e / NZ) * PZ + (e % NZ)] = in[off + e];
+  if constexpr (SRC == 0) {
+    for (int e = tid; e < NP; e += NT) plane[(e / NZ) * PZ + (e % NZ)] = in[off + e];
+  } else {
+    const R* rin = reinterpret_cast<const R*>(in);
+    const size_t Nall = size_t(NX) * NP;
+    for (int e = tid; e < NP; e += NT)
+      plane[(e / NZ) * PZ + (e % NZ)] = cpx<R>{SRC == 1 ? rin[off + e] + rin[Nall + off + e] : rin[off + e], R(0)};
+  }
   __syncthreads();
   if (W && pt.pr_off) {
     const size_t rowbase = size_t(b) * pt.Jtot;
@@ -797,7 +806,7 @@ __global__ __launch_bounds__(256) void k_fields(const double* __restrict__ rho,
     my = -2.0 * ri;
     mz = ruu - rdd;
     const double ve = vext ? vext[p] : 0.0;
-    const double vh = vH ? vH[p] : 0.0;
+    const double vh = vH ? vH[2 * p] : 0.0;  // real part of the complex Poisson output
     double vbar = 0.0, bx = 0.0, by = 0.0, bz = 0.0;
     if (xc) {
       const double c = 1.2407009817988000;  // (6/pi)^(1/3)
@@ -868,14 +877,6 @@ __global__ __launch_bounds__(256) void k_reduce_rows(const double* __restrict__ 
   }
 }
 
-__global__ void k_rho_to_n(const double* __restrict__ rho, size_t N, cpx<double>* __restrict__ out) {
-  const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
-  if (p < N) out[p] = {rho[p] + rho[N + p], 0.0};
-}
-__global__ void k_cpx_real(const cpx<double>* __restrict__ c, size_t N, double* __restrict__ out) {
-  const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
-  if (p < N) out[p] = c[p].x;
-}
 __global__ void k_add_bext(const double* __restrict__ f, int ny, int nz, size_t N, double b0,
                            double b1, double b2, double l0, double l1, double l2, double l3,
                            double* __restrict__ out) {
@@ -1122,7 +1123,7 @@ __global__ __launch_bounds__(256) void k_field_adjoint(const double* __restrict_
     gbx = g[N + p];
     gby = g[2 * N + p];
     gbz = g[3 * N + p];
-    double gn = pg ? pg[p] : 0.0;
+    double gn = pg ? pg[2 * p] : 0.0;  // real part of the complex Poisson output
     double gmx = 0, gmy = 0, gmz = 0;
     if (xc) {
       // v = vbar(n, |m|), b = bmag(n, |m|) m/|m| (|m| >= thr); with J the Jacobian of
@@ -1216,10 +1217,6 @@ __global__ __launch_bounds__(256) void k_density_backprop(const cpx<R>* __restri
   ld = {R(px), R(py)};
 }
 
-__global__ void k_real_to_cpx(const double* __restrict__ r, size_t N, cpx<double>* __restrict__ out) {
-  const size_t p = size_t(blockIdx.x) * 256 + threadIdx.x;
-  if (p < N) out[p] = {r[p], 0.0};
-}
 
 // ---------------------------------------------------------------- observables row
 __global__ __launch_bounds__(256) void k_obs_row(ObsInputs in, double* __restrict__ row) {
@@ -1469,6 +1466,27 @@ hipError_t launch_plane_fwd(const int n[3], int B, const void* in, void* out, vo
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_plane_fwd_real(const int n[3], const double* in, int src, void* out, const void* twy,
+                                 const void* twz, hipStream_t st) {
+  const unsigned grid = unsigned(n[0]);
+#define X(A, BB)                                                                            \
+  if (n[1] == A && n[2] == BB) {                                                            \
+    constexpr size_t lds = plane_lds_bytes<A, BB>(sizeof(cpx<double>));                     \
+    auto kern = src == 1 ? k_plane_fwd<double, A, BB, 1> : k_plane_fwd<double, A, BB, 2>;  \
+    hipError_t e = set_lds(kern, lds);                                                      \
+    if (e != hipSuccess) return e;                                                          \
+    nct_launch(kern, dim3(grid), dim3(plane_nt(A * BB)), lds, st,                            \
+               reinterpret_cast<const cpx<double>*>(in), reinterpret_cast<cpx<double>*>(out), \
+               static_cast<cpx<double>*>(nullptr), ProjTables{},                             \
+               reinterpret_cast<const cpx<double>*>(twy), reinterpret_cast<const cpx<double>*>(twz), \
+               1, n[0], KTables<double>{});                                                  \
+    return hipGetLastError();                                                               \
+  }
+  NCT_PLANE_PAIRS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_dm_init(const int n[3], const double cell[3], int natoms, const double* atoms,
                           const double* moments, double* rho, hipStream_t st) {
   const size_t N = size_t(n[0]) * n[1] * n[2];
@@ -1597,16 +1615,6 @@ hipError_t launch_reduce_rows(const double* part, int nrows, int width, double* 
   nct_launch(k_reduce_rows, dim3(1), dim3(256), 0, st, part, nrows, width, out);
   return hipGetLastError();
 }
-hipError_t launch_rho_to_n(const double* rho, size_t N, void* ncpx, hipStream_t st) {
-  nct_launch(k_rho_to_n, dim3(nblocks(N, 256)), dim3(256), 0, st, rho, N,
-                     reinterpret_cast<cpx<double>*>(ncpx));
-  return hipGetLastError();
-}
-hipError_t launch_cpx_real(const void* c, size_t N, double* out, hipStream_t st) {
-  nct_launch(k_cpx_real, dim3(nblocks(N, 256)), dim3(256), 0, st,
-                     reinterpret_cast<const cpx<double>*>(c), N, out);
-  return hipGetLastError();
-}
 hipError_t launch_add_bext(const double* fields, const int n[3], const double b[3],
                            const double lg[4], double* out, hipStream_t st) {
   const size_t N = size_t(n[0]) * n[1] * n[2];
@@ -1699,11 +1707,6 @@ hipError_t launch_density_backprop(const void* psi, const double* occ, const dou
   nct_launch((k_density_backprop<R>), dim3(nblocks(size_t(S) * N, 256)), dim3(256), 0, st,
                      reinterpret_cast<const cpx<R>*>(psi), occ, gnm, S, N, add,
                      reinterpret_cast<cpx<R>*>(lam));
-  return hipGetLastError();
-}
-hipError_t launch_real_to_cpx(const double* r, size_t N, void* out, hipStream_t st) {
-  nct_launch(k_real_to_cpx, dim3(nblocks(N, 256)), dim3(256), 0, st, r, N,
-                     reinterpret_cast<cpx<double>*>(out));
   return hipGetLastError();
 }
 
