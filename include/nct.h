@@ -182,7 +182,8 @@ nct_status nct_dm_initialization(nct_system *sys, const nct_atom_density *atoms,
  * solver): psi is first orthonormalised, then every iteration forms T_K(-tau H[rho]) psi (the
  * Taylor polynomial of exp(-tau H) of order params.taylor_order, through the same kernels as
  * the real-time step), orthonormalises it (Cholesky of the state overlap; the overlap and the
- * triangular transform are complex GEMMs of rocBLAS, the S x S factorisation runs on the host)
+ * triangular transform are complex GEMMs of rocBLAS, the S x S factorisation runs on the host;
+ * with k-points, within each run of consecutive states that share one Bloch vector)
  * and recomputes rho and the fields from it.  keep_fields nonzero: the first iteration uses the
  * system's current fields (e.g. from nct_dm_initialization); 0: those of psi's own density.
  * With frozen fields they stay frozen.  energies_host, if non-NULL, receives [niter] total
@@ -209,7 +210,9 @@ nct_status nct_set_laser_gauge(nct_system *sys, int gauge);
  * the states then hold the periodic parts u_i of psi_i = exp(i k_i.r) u_i: the kinetic factor
  * becomes 1/2 |G + k_i|^2 and the projector rows carry exp(i k_i.d) on projection and
  * exp(-i k_i.d) on scatter (d the grid point's displacement from the atom).  The k-point weights
- * enter through params.occ (f_i w_k).  NULL returns to Gamma only.  Synchronises the stream.
+ * enter through params.occ (f_i w_k).  States of one k-point are expected consecutive (the
+ * ground-state solver orthonormalises each such run).  NULL returns to Gamma only.
+ * Synchronises the stream.
  * Errors: NCT_ERR_ARG for a non-finite component. */
 nct_status nct_set_kpoints(nct_system *sys, const double *kvec);
 

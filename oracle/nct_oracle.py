@@ -761,33 +761,52 @@ def dm_initialization(grid: Grid, positions: np.ndarray, atoms: List[AtomDensity
     return rho.reshape((4,) + tuple(grid.n))
 
 
-def orthonormalize(psi: np.ndarray, dV: float) -> np.ndarray:
-    """Psi <- Psi L^(-H) with L L^H = dV Psi^H Psi (Cholesky): orthonormal states spanning the
-    same space (the overlap and the triangular solve are library primitives)."""
+def k_blocks(kvec: Optional[np.ndarray], S: int):
+    """Runs [i0, i1) of consecutive states that share one Bloch vector (a single run at Gamma).
+    States of different k are orthogonal through their Bloch factors, not through their periodic
+    parts, so orthonormalisation acts within each run."""
+    if kvec is None:
+        return [(0, S)]
+    kvec = np.asarray(kvec)
+    runs, i0 = [], 0
+    for i in range(1, S + 1):
+        if i == S or not np.array_equal(kvec[i], kvec[i0]):
+            runs.append((i0, i))
+            i0 = i
+    return runs
+
+
+def orthonormalize(psi: np.ndarray, dV: float, kvec: Optional[np.ndarray] = None) -> np.ndarray:
+    """Psi <- Psi L^(-H) with L L^H = dV Psi^H Psi (Cholesky), within each run of states of one
+    Bloch vector: orthonormal states spanning the same space (the overlap and the triangular
+    solve are library primitives)."""
     import scipy.linalg
     S = psi.shape[0]
     flat = psi.reshape(S, -1)
-    ovl = dV * (flat.conj() @ flat.T)
-    Lc = scipy.linalg.cholesky(ovl, lower=True)
-    # rows of the result: psi_new_j = sum_i psi_i (L^-H)_ij, i.e. new = (L^-H)^T flat = conj(L)^-1 flat
-    new = scipy.linalg.solve_triangular(Lc.conj(), flat, lower=True)
-    return new.reshape(psi.shape)
+    out = np.empty_like(flat)
+    for i0, i1 in k_blocks(kvec, S):
+        f = flat[i0:i1]
+        ovl = dV * (f.conj() @ f.T)
+        Lc = scipy.linalg.cholesky(ovl, lower=True)
+        # rows of the result: psi_new_j = sum_i psi_i (L^-H)_ij, i.e. new = conj(L)^-1 f
+        out[i0:i1] = scipy.linalg.solve_triangular(Lc.conj(), f, lower=True)
+    return out.reshape(psi.shape)
 
 
 def ground_state(sysd: System, psi0: np.ndarray, niter: int, tau: float,
                  rho_init: Optional[np.ndarray] = None):
     """Self-consistent imaginary-time propagation: each iteration applies T_K(-tau H[rho]) (the
-    Taylor polynomial of exp(-tau H), K = sysd.K) to the states, orthonormalises them, and takes
-    the new density; the first iteration uses rho_init if given (e.g. from dm_initialization).
+    Taylor polynomial of exp(-tau H), K = sysd.K) to the states, orthonormalises them (within each
+    run of one Bloch vector), and takes the new density; the first iteration uses rho_init if given (e.g. from dm_initialization).
     Returns (psi, total energies after each iteration)."""
-    psi = orthonormalize(psi0, sysd.grid.dV)
+    psi = orthonormalize(psi0, sysd.grid.dV, sysd.kvec)
     rho = spin_density(psi, sysd.occ) if rho_init is None else rho_init
     energies = []
     for _ in range(niter):
         F = fields_from_density(sysd, rho, 0.0)
         H = lambda x: apply_hamiltonian(sysd, x, F)
         psi = taylor_exp(H, psi, -1j * tau, sysd.K)
-        psi = orthonormalize(psi, sysd.grid.dV)
+        psi = orthonormalize(psi, sysd.grid.dV, sysd.kvec)
         rho = spin_density(psi, sysd.occ)
         energies.append(observables(sysd, psi, 0.0)[5])
     return psi, np.array(energies)

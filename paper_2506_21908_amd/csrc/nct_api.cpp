@@ -92,6 +92,7 @@ struct nct_system {
   double* kv64 = nullptr;
   float* kv32 = nullptr;
   bool has_k = false;
+  std::vector<int> krun;   // starts of the runs of consecutive states sharing one Bloch vector, + S
 
   // device: fields and densities (FP64)
   double* occ = nullptr;
@@ -1341,18 +1342,29 @@ struct Engine {
   }
 
   // dst = src L^(-H), L L^H = dV src^H src (states as the columns of a 2N x S matrix)
+  // Orthonormalise within each run of states that share one Bloch vector (their periodic
+  // parts; states of different k are orthogonal through the Bloch factors).
   nct_status orthonormalize(const void* src, void* dst) {
     nct_status r;
     if ((r = ensure_blas()) != NCT_OK) return r;
+    std::vector<int> runs = s->has_k ? s->krun : std::vector<int>{0, s->S};
+    for (size_t b = 0; b + 1 < runs.size(); ++b)
+      if ((r = orthonormalize_run(src, dst, runs[b], runs[b + 1] - runs[b])) != NCT_OK) return r;
+    return NCT_OK;
+  }
+
+  nct_status orthonormalize_run(const void* src, void* dst, int i0, int S) {
     using C = typename Blas<R>::C;
-    const rocblas_int S = s->S, K2 = rocblas_int(2 * s->N);
+    const rocblas_int K2 = rocblas_int(2 * s->N);
     const C al(R(s->dV), R(0)), one(R(1), R(0)), zero(R(0), R(0));
-    // overlap dV src^H src: k = 2N is long and S x S small, so split K into nb strided chunks
-    // (one GEMM batch each), fold the remainder into chunk 0, and sum the partials with a GEMV
+    const C* A0 = static_cast<const C*>(src) + size_t(i0) * K2;
+    C* D0 = static_cast<C*>(dst) + size_t(i0) * K2;
+    // overlap dV A^H A of this run: k = 2N is long and S x S small, so split K into nb strided
+    // chunks (one GEMM batch each), fold the remainder into chunk 0, and sum the partials with a
+    // GEMV
     const rocblas_int nb = s->ovl_nb;
     const rocblas_int kc = K2 / nb, krem = K2 - kc * nb;
     const rocblas_stride SS = rocblas_stride(S) * S;
-    const C* A0 = static_cast<const C*>(src);
     rocblas_status bs = Blas<R>::gemm_sb(s->blas, rocblas_operation_conjugate_transpose,
                                          rocblas_operation_none, S, S, kc, &one, A0, K2, kc, A0, K2, kc,
                                          &zero, s->ovl_part, S, SS, nb);
@@ -1373,8 +1385,8 @@ struct Engine {
       return fail(s, NCT_ERR_NONFINITE, "overlap of the states is not positive definite");
     for (size_t k = 0; k < h.size(); ++k) h[k] = cpx<R>{R(A[k].real()), R(A[k].imag())};
     HIPCHK(s, hipMemcpyAsync(s->ovl, h.data(), h.size() * sizeof(cpx<R>), hipMemcpyHostToDevice, s->st));
-    bs = Blas<R>::gemm(s->blas, rocblas_operation_none, rocblas_operation_none, K2, S, S, &one, src, K2,
-                       s->ovl, S, &zero, dst, K2);
+    bs = Blas<R>::gemm(s->blas, rocblas_operation_none, rocblas_operation_none, K2, S, S, &one, A0, K2,
+                       s->ovl, S, &zero, D0, K2);
     if (bs != rocblas_status_success) return fail(s, NCT_ERR_HIP, "rocBLAS transform GEMM: status %d", int(bs));
     HIPCHK(s, hipStreamSynchronize(s->st));  // h is released on return
     return NCT_OK;
@@ -1817,6 +1829,11 @@ nct_status nct_set_kpoints(nct_system* s, const double* kvec) {
     if ((r = dalloc(s, n * sizeof(float), &p)) != NCT_OK) return r;
     s->kv32 = static_cast<float*>(p);
   }
+  s->krun.assign(1, 0);
+  for (int i = 1; i < s->S; ++i)
+    if (kvec[3 * i] != kvec[3 * i - 3] || kvec[3 * i + 1] != kvec[3 * i - 2] || kvec[3 * i + 2] != kvec[3 * i - 1])
+      s->krun.push_back(i);
+  s->krun.push_back(s->S);
   std::vector<float> k32(kvec, kvec + n);
   HIPCHK(s, hipMemcpyAsync(s->kv64, kvec, n * sizeof(double), hipMemcpyHostToDevice, s->st));
   HIPCHK(s, hipMemcpyAsync(s->kv32, k32.data(), n * sizeof(float), hipMemcpyHostToDevice, s->st));

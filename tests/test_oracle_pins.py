@@ -845,6 +845,39 @@ def test_ground_state_reaches_lowest_eigenvectors_without_interactions():
     assert np.abs(P - Q).max() < 1e-6
 
 
+def test_ground_state_with_kpoints_reaches_lowest_bands_of_each_k():
+    """Two k-points x two states, no interaction: each k-run converges to the two lowest
+    eigenvectors of its own H_k (a dense matrix from the oracle's H on basis vectors), and the
+    energy to the weighted band sum; states of different k are not mixed."""
+    w = I.make_system(n=(6, 6, 6), L=(5.0,) * 3, nstates=4, natoms=1, case=61, xc=0, hartree=0,
+                      bfield=I.BField(B0=(0.0, 0.05, 0.1)), full_spinors=True)
+    k1 = np.array([0.35, -0.2, 0.15])
+    w.kvec = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 0.0], k1, k1])
+    w.occ = np.full(4, 0.5)
+    sysd = O.system_from_workload(w)
+    assert O.k_blocks(sysd.kvec, 4) == [(0, 2), (2, 4)]
+    F = O.fields_from_density(sysd, O.spin_density(w.psi0, sysd.occ), 0.0)
+    N = sysd.grid.N
+    dense = {}
+    for k in (np.zeros(3), k1):
+        basis = np.eye(2 * N, dtype=complex).reshape((2 * N, 2) + tuple(sysd.grid.n))
+        sk = O.System(**{**vars(sysd), "kvec": np.tile(k, (2 * N, 1)), "occ": np.ones(2 * N)})
+        Hk = O.apply_hamiltonian(sk, basis, F).reshape(2 * N, 2 * N).T
+        assert np.abs(Hk - Hk.conj().T).max() < 1e-12
+        dense[tuple(k)] = np.linalg.eigh(Hk)
+    psi, E = O.ground_state(sysd, w.psi0, 800, 0.1)
+    band = 0.0
+    for (i0, i1), k in (((0, 2), np.zeros(3)), ((2, 4), k1)):
+        evals, evecs = dense[tuple(k)]
+        assert evals[2] - evals[1] > 0.2   # e^(-0.1 x 0.2 x 800) ~ 1e-7 left of the next band
+        band += 0.5 * evals[:2].sum()
+        f = psi[i0:i1].reshape(2, -1).T * math.sqrt(sysd.grid.dV)
+        P = f @ f.conj().T
+        Q = evecs[:, :2] @ evecs[:, :2].conj().T
+        assert np.abs(P - Q).max() < 1e-6
+    assert abs(E[-1] - band) < 1e-9
+
+
 def test_ground_state_self_consistent_with_exchange_and_hartree():
     """With exchange and Hartree on, the converged states are eigenvectors of the Hamiltonian built
     from their own density (subspace residual H psi - psi Lambda), and the energy settles."""
