@@ -55,7 +55,25 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
         "-L", os.path.join(ROCM, "lib"), "-lrocblas", "-Wl,-rpath," + os.path.join(ROCM, "lib")]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    build_c_example()
     return LIB
+
+
+EXAMPLE_SRC = os.path.join(HERE, "examples", "c_step.c")
+EXAMPLE_BIN = os.path.join(HERE, "examples", "c_step")
+
+
+def build_c_example() -> str:
+    """Compile the plain C client (examples/c_step.c) against libnct.so with the host compiler."""
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        raise RuntimeError("no C compiler for the C example")
+    cmd = [cc, "-O2", "-std=c99", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(HERE, "..", "include"),
+           "-I", os.path.join(ROCM, "include"), EXAMPLE_SRC, "-o", EXAMPLE_BIN, "-L", HERE, "-lnct",
+           "-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-lm",
+           "-Wl,-rpath,$ORIGIN/..", "-Wl,-rpath," + os.path.join(ROCM, "lib")]
+    subprocess.run(cmd, check=True)
+    return EXAMPLE_BIN
 
 
 if __name__ == "__main__":
