@@ -19,7 +19,13 @@
  *     correlation (Phys. Rev. B 45, 13244); b_xc = 0 where |m| < m_threshold.
  *   - Hartree: Eq. (KSpot) solved by FFT, G = 0 term dropped.
  *   - Optional uniform electric (laser) pulse E(t) with the temporal profile of
- *     the optical runs of Sec. 4.7, in the length gauge (see nct_set_laser).
+ *     the optical runs of Sec. 4.7, in the length or the velocity gauge (see
+ *     nct_set_laser, nct_set_laser_gauge).
+ *   - Optional k-point sampling (state index i = (n, k), Eq. KSDFT; see
+ *     nct_set_kpoints).
+ *   - Initial spin density of the magnetisation-initialisation algorithm
+ *     (nct_dm_initialization) and an imaginary-time ground state
+ *     (nct_ground_state); the reverse-mode (adjoint) step (nct_backward_step).
  *   - Propagator (the paper names none): enforced time-reversal symmetry with
  *     a truncated Taylor exponential of order taylor_order:
  *        phi = T(-i dt/2 H[rho(psi_n), B(t_n)]) psi_n
@@ -41,9 +47,10 @@
  * nct_destroy_system.
  *
  * Streams: all work is enqueued on params.stream (a hipStream_t; NULL means
- * the default stream).  Calls return once the work is enqueued, except calls
- * that write host memory (totals_host, obs_host, dLdB_host, dLdtheta_host),
- * which synchronise the stream before returning.
+ * the default stream); some passes run on the library's own streams, ordered
+ * against params.stream by events.  Calls return once the work is enqueued,
+ * except calls that write host memory (totals_host, obs_host, dLdB_host,
+ * dLdtheta_host), which synchronise the stream before returning.
  *
  * Errors: every call returns an nct_status; no exception crosses the ABI.
  * NCT_ERR_ARG is returned before any work is enqueued and leaves every output
