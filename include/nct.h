@@ -198,7 +198,7 @@ nct_status nct_dm_initialization(nct_system *sys, const nct_atom_density *atoms,
  * tau |H| within the stability range of the Taylor polynomial (|T_4(-x)| < 1 for x < 2.78).
  * Synchronises the stream.  Errors: NCT_ERR_ARG (niter < 0, tau not positive), NCT_ERR_NONFINITE
  * (states linearly dependent, or a non-finite energy), NCT_ERR_UNSUPPORTED (more than 4096
- * states). */
+ * states, or the states of one Bloch vector not consecutive). */
 nct_status nct_ground_state(nct_system *sys, void *psi_dev, int niter, double tau, int keep_fields,
                             double *energies_host);
 

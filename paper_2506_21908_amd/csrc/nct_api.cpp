@@ -93,6 +93,7 @@ struct nct_system {
   float* kv32 = nullptr;
   bool has_k = false;
   std::vector<int> krun;   // starts of the runs of consecutive states sharing one Bloch vector, + S
+  bool krun_split = false; // some Bloch vector occurs in two separate runs
 
   // device: fields and densities (FP64)
   double* occ = nullptr;
@@ -1788,6 +1789,8 @@ nct_status nct_ground_state(nct_system* s, void* psi, int niter, double tau, int
   if (niter < 0) return fail(s, NCT_ERR_ARG, "niter < 0");
   if (!(tau > 0) || !std::isfinite(tau)) return fail(s, NCT_ERR_ARG, "tau must be positive and finite");
   if (s->S > 4096) return fail(s, NCT_ERR_UNSUPPORTED, "at most 4096 states in the ground-state solver");
+  if (s->has_k && s->krun_split)
+    return fail(s, NCT_ERR_UNSUPPORTED, "the states of each Bloch vector must be consecutive for the ground state");
   if (s->fp64) return Engine<double>{s}.ground_state(psi, niter, tau, keep_fields != 0, energies_host);
   return Engine<float>{s}.ground_state(psi, niter, tau, keep_fields != 0, energies_host);
 }
@@ -1834,6 +1837,13 @@ nct_status nct_set_kpoints(nct_system* s, const double* kvec) {
     if (kvec[3 * i] != kvec[3 * i - 3] || kvec[3 * i + 1] != kvec[3 * i - 2] || kvec[3 * i + 2] != kvec[3 * i - 1])
       s->krun.push_back(i);
   s->krun.push_back(s->S);
+  s->krun_split = false;
+  for (size_t a = 0; a + 1 < s->krun.size(); ++a)
+    for (size_t b = a + 1; b + 1 < s->krun.size(); ++b) {
+      const double* ka = kvec + 3 * s->krun[a];
+      const double* kb = kvec + 3 * s->krun[b];
+      if (ka[0] == kb[0] && ka[1] == kb[1] && ka[2] == kb[2]) s->krun_split = true;
+    }
   std::vector<float> k32(kvec, kvec + n);
   HIPCHK(s, hipMemcpyAsync(s->kv64, kvec, n * sizeof(double), hipMemcpyHostToDevice, s->st));
   HIPCHK(s, hipMemcpyAsync(s->kv32, k32.data(), n * sizeof(float), hipMemcpyHostToDevice, s->st));

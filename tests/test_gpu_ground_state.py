@@ -148,3 +148,9 @@ def test_ground_state_argument_errors(torch_cuda):
     with pytest.raises(nct.NctError) as e:   # linearly dependent states
         s.ground_state(dup, 1, 0.03)
     assert e.value.code == nct.NCT_ERR_NONFINITE
+    w3 = I.make_system(n=(8, 8, 8), L=(6.0,) * 3, nstates=3, case=65)
+    s3 = nct.system_from_workload(w3)
+    s3.set_kpoints(np.array([[0.0, 0.0, 0.0], [0.3, 0.0, 0.0], [0.0, 0.0, 0.0]]))
+    with pytest.raises(nct.NctError) as e:   # one Bloch vector in two separate runs
+        s3.ground_state(nct.states_to_device(w3.psi0), 1, 0.03)
+    assert e.value.code == nct.NCT_ERR_UNSUPPORTED
