@@ -154,7 +154,7 @@ struct nct_system {
   double* gB = nullptr;
   double* gnm = nullptr;      // [4][N] density gradients
   double* gpart = nullptr;    // [nblk][4]
-  double* gtot = nullptr;     // [4]
+  double* gtot = nullptr;     // [2][4]: field-adjoint totals of H_n and H~
 
   // kernel timing (profiling aid)
   struct TimedLaunch {
@@ -1228,8 +1228,9 @@ struct Engine {
     return NCT_OK;
   }
 
-  // (g_v, g_b) at the fields of density rho  ->  (g_n, g_m) into s->gnm; returns sum_r g_b in gsum.
-  nct_status field_adjoint(const double* rho, const double* g, double gsum[3]) {
+  // (g_v, g_b) at the fields of density rho  ->  (g_n, g_m) into s->gnm; sum_r g_b into
+  // s->gtot[4 slot .. 4 slot + 2] (device; read once at the end of the backward step).
+  nct_status field_adjoint(const double* rho, const double* g, int slot) {
     nct_status r;
     const double N = double(s->N);
     const double* pgp = nullptr;
@@ -1250,12 +1251,7 @@ struct Engine {
     if ((r = check(timed(s, NCT_K_ADJOINT, 96 * N, 0, [&] {
            return launch_field_adjoint(rho, g, pgp, s->prm.xc, s->prm.m_threshold, s->N, s->gnm, s->gpart,
                                        &nb, s->st); }), "field_adjoint")) != NCT_OK) return r;
-    if ((r = check(launch_reduce_rows(s->gpart, nb, 4, s->gtot, s->st), "reduce")) != NCT_OK) return r;
-    double tot[4];
-    HIPCHK(s, hipMemcpyAsync(tot, s->gtot, sizeof(tot), hipMemcpyDeviceToHost, s->st));
-    HIPCHK(s, hipStreamSynchronize(s->st));
-    for (int k = 0; k < 3; ++k) gsum[k] = tot[k];
-    return NCT_OK;
+    return check(launch_reduce_rows(s->gpart, nb, 4, s->gtot + 4 * slot, s->st), "reduce");
   }
 
   nct_status backprop_density(const void* psi, void* lam, int add) {
@@ -1282,7 +1278,6 @@ struct Engine {
     }
     void* lamphi = s->phi;
     void* lamtil = s->phihat;
-    double gs[3] = {0, 0, 0};
     // third exponential, fields of H~ at t_{n+1}
     if ((r = load_fields(tfld(T, idx, 1))) != NCT_OK) return r;
     HIPCHK(s, hipMemsetAsync(s->gA, 0, gb, s->st));
@@ -1290,8 +1285,7 @@ struct Engine {
     if (s->frozen) {
       for (int k = 0; k < 6; ++k) dLdB[k] = 0.0;
     } else {
-      if ((r = field_adjoint(trho(T, idx, 1), s->gA, gs)) != NCT_OK) return r;
-      for (int k = 0; k < 3; ++k) dLdB[3 + k] = kMuB * gs[k];
+      if ((r = field_adjoint(trho(T, idx, 1), s->gA, 1)) != NCT_OK) return r;
       // density at psi~ -> lam_psi~, then the second exponential (fields of H_n)
       if ((r = backprop_density(tvec(T, idx, 3 * K - 1), lamtil, 0)) != NCT_OK) return r;
       if ((r = load_fields(tfld(T, idx, 0))) != NCT_OK) return r;
@@ -1306,11 +1300,17 @@ struct Engine {
     // first exponential -> lam_n
     if ((r = adjoint_taylor(lamphi, xs1.data(), lam_n, true, s->gB, t_n)) != NCT_OK) return r;
     if (!s->frozen) {
-      if ((r = field_adjoint(trho(T, idx, 0), s->gB, gs)) != NCT_OK) return r;
-      for (int k = 0; k < 3; ++k) dLdB[k] = kMuB * gs[k];
+      if ((r = field_adjoint(trho(T, idx, 0), s->gB, 0)) != NCT_OK) return r;
       if ((r = backprop_density(tvec(T, idx, 0), lam_n, 1)) != NCT_OK) return r;
     }
+    double tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (!s->frozen) HIPCHK(s, hipMemcpyAsync(tot, s->gtot, sizeof(tot), hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
+    if (!s->frozen)
+      for (int k = 0; k < 3; ++k) {
+        dLdB[k] = kMuB * tot[k];
+        dLdB[3 + k] = kMuB * tot[4 + k];
+      }
     harvest_timing(s);
     return NCT_OK;
   }
@@ -1670,7 +1670,7 @@ nct_status create_impl(const nct_params* p, nct_system** out) {
   s->gnm = (double*)p0;
   if ((r = dalloc(s, ((N + 255) / 256) * 4 * 8, &p0)) != NCT_OK) return bail(r);
   s->gpart = (double*)p0;
-  if ((r = dalloc(s, 4 * 8, &p0)) != NCT_OK) return bail(r);
+  if ((r = dalloc(s, 8 * 8, &p0)) != NCT_OK) return bail(r);
   s->gtot = (double*)p0;
   if (p->tape_steps > 0 && (r = alloc_tape(s, s->tape, p->tape_steps)) != NCT_OK) return bail(r);
   if (hipStreamCreateWithFlags(&s->st2, hipStreamNonBlocking) != hipSuccess ||
