@@ -258,7 +258,11 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a
 // Same stage as k_plane_stage, with the two spinor components of the (state, x-plane) held as
 // two LDS planes and transformed concurrently by the two halves of the workgroup; the pointwise
 // 2x2 update then reads both planes.  Used when two planes fit in LDS.
-// Threads per spinor half: plane_nt's choice capped at NCT_PLANE2_NTH_MAX (tuning macro).
+// Threads per spinor half: plane_nt's choice capped at NCT_PLANE2_NTH_MAX (tuning macro), except
+// FP64 48^2 planes.  There LDS admits two workgroups per CU, and 256 threads per half at 98 VGPRs
+// keep only 16 waves per CU; 384 threads (6 points each, 2304 = 6 x 384) with a register target
+// of 6 waves per SIMD (80 VGPRs) keep 24 and measured 3 % faster on MI355X.  320 and 448 threads
+// (a partial last round) and 512 (spills at 64 VGPRs) measured slower.
 #ifndef NCT_PLANE2_NTH_MAX_F64
 #define NCT_PLANE2_NTH_MAX_F64 512
 #endif
@@ -267,8 +271,14 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_stage(StageArgs<R> a
 #endif
 template <typename R>
 __host__ __device__ constexpr int plane2_nth(int np) {
+  if (sizeof(R) == 8 && np == 48 * 48) return 384;
   const int cap = sizeof(R) == 8 ? NCT_PLANE2_NTH_MAX_F64 : NCT_PLANE2_NTH_MAX_F32;
   return plane_nt(np) > cap ? cap : plane_nt(np);
+}
+// minimum waves per SIMD the register allocation of the two-half kernel must allow
+template <typename R>
+__host__ __device__ constexpr int plane2_min_waves(int np) {
+  return (sizeof(R) == 8 && np == 48 * 48) ? 6 : 1;
 }
 template <int NY, int NZ>
 constexpr size_t plane2_lds_bytes(size_t elem) {
@@ -284,7 +294,7 @@ constexpr bool plane2_fits() {
 }
 
 template <typename R, int NY, int NZ, int M>
-__global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(StageArgs<R> a, ProjTables pt,
+__global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ), plane2_min_waves<R>(NY* NZ)) void k_plane_stage2(StageArgs<R> a, ProjTables pt,
                                                                           const cpx<R>* __restrict__ twy_g,
                                                                           const cpx<R>* __restrict__ twz_g,
                                                                           int S, int NX) {
@@ -301,7 +311,8 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ)) void k_plane_stage2(Stag
 #ifndef NCT_PLANE2_G_F32
 #define NCT_PLANE2_G_F32 3
 #endif
-  constexpr int G = sizeof(R) == 8 ? NCT_PLANE2_G_F64 : NCT_PLANE2_G_F32;  // pointwise points per load batch
+  // pointwise points per load batch (2 for FP64 48^2, where 3 spills at that case's register target)
+  constexpr int G = (sizeof(R) == 8 && NP == 48 * 48) ? 2 : (sizeof(R) == 8 ? NCT_PLANE2_G_F64 : NCT_PLANE2_G_F32);
   extern __shared__ double4 smem_d4[];
   cpx<R>* planes = reinterpret_cast<cpx<R>*>(smem_d4);
   cpx<R>* twy = planes + 2 * PL;
