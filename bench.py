@@ -110,8 +110,8 @@ def main():
                     help="run one plain 1 GiB device copy first (PMC scale reference)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the state-sharded multi-GPU design is "
-              "described in DESIGN.md but not built); use --gpus 1", file=sys.stderr)
+        print("bench.py: runs on one GPU only (a state-sharded multi-GPU path is not "
+              "implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -25,7 +25,7 @@ Sources (paper arXiv 2506.21908, "Spin non-collinear real-time TDDFT ... INQ"):
     the periodic parts u of psi = exp(i k.r) u, kinetic 1/2 |G + k|^2, projector
     Bloch phases exp(-/+ i k.d) on the sphere points; k-weights enter the occupations
 The paper names no propagator, Taylor order, Poisson solver or LDA
-parametrisation; the readings taken here are listed in the design doc and below:
+parametrisation; the readings taken here are:
   * propagator: enforced time-reversal symmetry (ETRS) with a truncated Taylor
     exponential of order K (default 4), predictor built from a second
     half-step of the same exponential;
