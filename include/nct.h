@@ -262,6 +262,15 @@ nct_status nct_apply_hamiltonian(nct_system *sys, const void *psi_dev, void *hps
 nct_status nct_step(nct_system *sys, void *psi_dev, double t0, int nsteps, double *obs_host,
                     int tape);
 
+/* Per-step watchdog of nct_step.  Every self-consistent step reduces the electron count
+ * N_e = sum_i f_i <psi_i|psi_i> with its fields; nct_step keeps that value for every step of the
+ * call on the device and, once the call's work is done, returns NCT_ERR_NONFINITE (naming the
+ * first failing step) if it is not finite or if |N_e(step) - N_e(start)| / |N_e(start)| exceeds
+ * max_rel_drift (default 1e-3; <= 0 checks finiteness only).  A non-finite value anywhere in a
+ * state makes N_e non-finite.  With frozen fields only the final state is checked.
+ * Errors: NCT_ERR_ARG if max_rel_drift is NaN. */
+nct_status nct_set_watchdog(nct_system *sys, double max_rel_drift);
+
 /* lam = 2 dV f_i (w . sigma) psi_i: the adjoint seed 2 dL/dpsi* of L = w . M(t) with
  * M = int m dV.  psi and lam have the psi layout; w is host double[3]. */
 nct_status nct_magnetization_seed(nct_system *sys, const void *psi_dev, const double *w,
@@ -292,7 +301,8 @@ enum {
   NCT_K_PROJ = 5,         /* projector contraction + scatter (MFMA) */
   NCT_K_OBS = 6,          /* observables (energy pass, row assembly) */
   NCT_K_ADJOINT = 7,      /* adjoint-only kernels (pair reductions, density back-propagation) */
-  NCT_K_COUNT = 8
+  NCT_K_ORTH = 8,         /* ground-state orthonormalisation (overlap and change of basis, MFMA) */
+  NCT_K_COUNT = 9
 };
 
 /* Profiling aid.  nct_set_timing(sys, mask) resets the counters and, for every kernel class k

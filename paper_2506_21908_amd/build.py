@@ -52,7 +52,7 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
         raise RuntimeError("hipcc failed:\n" + msg)
     tmp = LIB + ".tmp"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + [
-        "-L", os.path.join(ROCM, "lib"), "-lrocblas", "-Wl,-rpath," + os.path.join(ROCM, "lib")]
+        "-Wl,-rpath," + os.path.join(ROCM, "lib")]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     build_c_example()

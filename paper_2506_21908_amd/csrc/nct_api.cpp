@@ -4,7 +4,6 @@
 // |G|^2 per axis), the projector tables of every atom, and drives the
 // kernels of one ETRS step on the caller's stream.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -107,13 +106,16 @@ struct nct_system {
   double* ftot = nullptr;      // [kFieldTot]
   double* epart = nullptr;     // [2S][ntiles][2]
   double* obs_dev = nullptr;   // [cap][13]
-  // ground state: rocBLAS handle (plain library GEMMs of the orthonormalisation), S x S buffers
-  rocblas_handle blas = nullptr;
-  void* ovl = nullptr;         // complex R [S][S] overlap / triangular factor
+  // per-step watchdog: N_e = sum_i f_i <psi_i|psi_i> after every self-consistent step of a call
+  double* ne_hist = nullptr;   // [ne_cap]: slot 0 the initial states, slot k+1 after step k
+  int ne_cap = 0;
+  double max_ne_drift = 1e-3;  // relative drift of N_e that fails a step (<= 0: finiteness only)
+  // ground state: S x S buffers of the orthonormalisation (complex double)
+  void* ovl = nullptr;         // [S][S] overlap, then the triangular factor L^-H
   double* dm_atoms = nullptr;  // [natoms][9] atom data of the initial spin-density matrix
-  void* ovl_part = nullptr;    // complex R [nb][S][S] split-K partial overlaps
-  void* ovl_ones = nullptr;    // complex R [nb] ones
+  void* ovl_part = nullptr;    // [nchunks][S][S] partial overlaps over chunks of the 2N values
   int ovl_nb = 0;
+  std::vector<std::complex<double>> ovl_host;  // host copy of the factor (lives until its upload ends)
   int obs_cap = 0;
 
   // device: psi-sized work (precision of the system)
@@ -637,60 +639,6 @@ bool cholesky_inverse_h(std::vector<std::complex<double>>& A, int n) {
   return true;
 }
 
-// complex GEMM of the orthonormalisation through rocBLAS (plain library GEMMs)
-template <typename R>
-struct Blas;
-template <>
-struct Blas<double> {
-  using C = rocblas_double_complex;
-  static rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb,
-                             rocblas_int m, rocblas_int n, rocblas_int k, const C* al, const void* A,
-                             rocblas_int lda, const void* B, rocblas_int ldb, const C* be, void* Cm,
-                             rocblas_int ldc) {
-    return rocblas_zgemm(h, ta, tb, m, n, k, al, static_cast<const C*>(A), lda,
-                         static_cast<const C*>(B), ldb, be, static_cast<C*>(Cm), ldc);
-  }
-  static rocblas_status gemm_sb(rocblas_handle h, rocblas_operation ta, rocblas_operation tb,
-                                rocblas_int m, rocblas_int n, rocblas_int k, const C* al, const void* A,
-                                rocblas_int lda, rocblas_stride sa, const void* B, rocblas_int ldb,
-                                rocblas_stride sb, const C* be, void* Cm, rocblas_int ldc,
-                                rocblas_stride sc, rocblas_int batch) {
-    return rocblas_zgemm_strided_batched(h, ta, tb, m, n, k, al, static_cast<const C*>(A), lda, sa,
-                                         static_cast<const C*>(B), ldb, sb, be, static_cast<C*>(Cm),
-                                         ldc, sc, batch);
-  }
-  static rocblas_status gemv(rocblas_handle h, rocblas_int m, rocblas_int n, const C* al, const void* A,
-                             rocblas_int lda, const void* x, const C* be, void* y) {
-    return rocblas_zgemv(h, rocblas_operation_none, m, n, al, static_cast<const C*>(A), lda,
-                         static_cast<const C*>(x), 1, be, static_cast<C*>(y), 1);
-  }
-};
-template <>
-struct Blas<float> {
-  using C = rocblas_float_complex;
-  static rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb,
-                             rocblas_int m, rocblas_int n, rocblas_int k, const C* al, const void* A,
-                             rocblas_int lda, const void* B, rocblas_int ldb, const C* be, void* Cm,
-                             rocblas_int ldc) {
-    return rocblas_cgemm(h, ta, tb, m, n, k, al, static_cast<const C*>(A), lda,
-                         static_cast<const C*>(B), ldb, be, static_cast<C*>(Cm), ldc);
-  }
-  static rocblas_status gemm_sb(rocblas_handle h, rocblas_operation ta, rocblas_operation tb,
-                                rocblas_int m, rocblas_int n, rocblas_int k, const C* al, const void* A,
-                                rocblas_int lda, rocblas_stride sa, const void* B, rocblas_int ldb,
-                                rocblas_stride sb, const C* be, void* Cm, rocblas_int ldc,
-                                rocblas_stride sc, rocblas_int batch) {
-    return rocblas_cgemm_strided_batched(h, ta, tb, m, n, k, al, static_cast<const C*>(A), lda, sa,
-                                         static_cast<const C*>(B), ldb, sb, be, static_cast<C*>(Cm),
-                                         ldc, sc, batch);
-  }
-  static rocblas_status gemv(rocblas_handle h, rocblas_int m, rocblas_int n, const C* al, const void* A,
-                             rocblas_int lda, const void* x, const C* be, void* y) {
-    return rocblas_cgemv(h, rocblas_operation_none, m, n, al, static_cast<const C*>(A), lda,
-                         static_cast<const C*>(x), 1, be, static_cast<C*>(y), 1);
-  }
-};
-
 // ---------------------------------------------------------------- engine
 template <typename R>
 struct Engine {
@@ -724,6 +672,9 @@ struct Engine {
     return NCT_OK;
   }
 
+  // where the next field update also records its electron count (per-step watchdog), or null
+  double* ne_slot = nullptr;
+
   // Hartree + exchange fields from the density in s->rho (FP64 throughout)
   nct_status fields_from_rho(bool store) {
     nct_status r;
@@ -749,7 +700,8 @@ struct Engine {
     if ((r = check(timed(s, K, (32 + 16 + 32 + (o32 ? 16 : 0)) * N, 0, [&] {
            return launch_fields(s->rho, s->vext, vh, s->prm.xc, s->prm.m_threshold, s->n, s->prm.cell, out, o32,
                                 s->fpart, &nb, s->st); }), "fields")) != NCT_OK) return r;
-    if ((r = check(timed(s, K, 8.0 * kFieldTot * nb, 0, [&] { return launch_reduce_rows(s->fpart, nb, kFieldTot, s->ftot, s->st); }),
+    if ((r = check(timed(s, K, 8.0 * kFieldTot * nb, 0, [&] {
+           return launch_reduce_rows(s->fpart, nb, kFieldTot, s->ftot, s->st, ne_slot); }),
                    "reduce")) != NCT_OK) return r;
     if (store) s->fields_valid = true;
     return NCT_OK;
@@ -760,7 +712,9 @@ struct Engine {
                    return launch_density<R>(psi, s->occ, s->S, s->N, s->rho, s->st); }), "density");
   }
 
-  double proj_flops() const { return 8.0 * s->pt.PP * 2.0 * s->pt.Jtot * s->S; }
+  // useful flops of one projector GEMM (contraction or scatter): 8 per complex multiply-add over
+  // the P projectors of every atom (not the padded PP columns the MFMA tiles also compute)
+  double proj_flops() const { return 8.0 * s->pt.P * 2.0 * s->pt.Jtot * s->S; }
   double beta_bytes() const { return 2.0 * s->pt.Jtot * s->pt.PP * sizeof(R) * 2; }
 
   nct_status contract(const void* W, hipStream_t st) {
@@ -1101,6 +1055,18 @@ struct Engine {
       s->obs_dev = static_cast<double*>(p);
       s->obs_cap = nsteps;
     }
+    // per-step watchdog: every self-consistent step already reduces N_e with its fields; that
+    // value is kept per step on the device and checked once at the end of the call
+    const bool watch = !s->frozen;
+    if (watch && s->ne_cap < nsteps + 1) {
+      void* p;
+      if ((r = dalloc(s, size_t(nsteps + 1) * sizeof(double), &p)) != NCT_OK) return r;
+      s->ne_hist = static_cast<double*>(p);
+      s->ne_cap = nsteps + 1;
+    }
+    if (watch) {  // N_e of the initial states (their fields were formed above)
+      HIPCHK(s, hipMemcpyAsync(s->ne_hist, s->ftot, sizeof(double), hipMemcpyDeviceToDevice, s->st));
+    }
     std::vector<void*> so1(K > 1 ? K - 1 : 1), so2(K > 1 ? K - 1 : 1), so3(K > 1 ? K - 1 : 1);
     for (int k = 0; k < nsteps; ++k) {
       const double t = t0 + k * dt;
@@ -1150,7 +1116,10 @@ struct Engine {
       if (k + 1 < nsteps && (r = early_kinetic(t + dt)) != NCT_OK) return r;
       if (!s->frozen || obs_host) {
         if ((r = density(cur)) != NCT_OK) return r;
-        if ((r = fields_from_rho(!s->frozen)) != NCT_OK) return r;
+        ne_slot = watch ? s->ne_hist + k + 1 : nullptr;
+        r = fields_from_rho(!s->frozen);
+        ne_slot = nullptr;
+        if (r != NCT_OK) return r;
       }
       if (obs_host) {
         if ((r = obs_row(t + dt, s->obs_dev + size_t(k) * kObsWidth)) != NCT_OK) return r;
@@ -1165,9 +1134,21 @@ struct Engine {
     if (obs_host)
       HIPCHK(s, hipMemcpyAsync(obs_host, s->obs_dev, size_t(nsteps) * kObsWidth * sizeof(double),
                                hipMemcpyDeviceToHost, s->st));
+    std::vector<double> ne(watch ? nsteps + 1 : 0);
+    if (watch)
+      HIPCHK(s, hipMemcpyAsync(ne.data(), s->ne_hist, ne.size() * sizeof(double), hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
     harvest_timing(s);
     if (T) T->valid = nsteps;
+    for (int k = 1; k <= (watch ? nsteps : 0); ++k) {
+      if (!std::isfinite(ne[k]))
+        return fail(s, NCT_ERR_NONFINITE, "step %d of the call: non-finite electron count", k - 1);
+      const double drift = std::fabs(ne[k] - ne[0]) / std::max(std::fabs(ne[0]), 1e-300);
+      if (s->max_ne_drift > 0.0 && drift > s->max_ne_drift)
+        return fail(s, NCT_ERR_NONFINITE,
+                    "step %d of the call: electron count drifted by %.3e relative (limit %.3e)", k - 1,
+                    drift, s->max_ne_drift);
+    }
     if (!std::isfinite(tot[0])) return fail(s, NCT_ERR_NONFINITE, "non-finite electron count after step");
     return NCT_OK;
   }
@@ -1316,29 +1297,17 @@ struct Engine {
   }
 
   // ------------------------------------------------------------ ground state
-  nct_status ensure_blas() {
-    if (s->ovl_ones) return NCT_OK;  // set last: a failed set-up is redone on the next call
-    if (!s->blas) {
-      if (rocblas_create_handle(&s->blas) != rocblas_status_success) {
-        s->blas = nullptr;
-        return fail(s, NCT_ERR_HIP, "rocblas_create_handle failed");
-      }
-      if (rocblas_set_stream(s->blas, s->st) != rocblas_status_success)
-        return fail(s, NCT_ERR_HIP, "rocblas_set_stream failed");
-    }
+  // S x S buffers of the orthonormalisation, allocated on first use
+  nct_status ensure_ovl() {
+    if (s->ovl_part) return NCT_OK;  // set last: a failed set-up is redone on the next call
     nct_status r;
-    if (!s->ovl && (r = dalloc(s, size_t(s->S) * s->S * 16, &s->ovl)) != NCT_OK) return r;
-    // split-K of the overlap: up to 256 chunks, partials within 4 Mi complex entries
     const size_t SS = size_t(s->S) * s->S;
-    size_t nb = std::min<size_t>(256, std::max<size_t>(1, (size_t(1) << 22) / SS));
-    nb = std::min<size_t>(nb, std::max<size_t>(1, 2 * s->N / 64));
-    s->ovl_nb = int(nb);
-    if (!s->ovl_part && (r = dalloc(s, nb * SS * sizeof(cpx<R>), &s->ovl_part)) != NCT_OK) return r;
-    void* ones_d = nullptr;
-    if ((r = dalloc(s, nb * sizeof(cpx<R>), &ones_d)) != NCT_OK) return r;
-    std::vector<cpx<R>> ones(nb, cpx<R>{R(1), R(0)});
-    HIPCHK(s, hipMemcpy(ones_d, ones.data(), nb * sizeof(cpx<R>), hipMemcpyHostToDevice));
-    s->ovl_ones = ones_d;
+    if (!s->ovl && (r = dalloc(s, SS * 16, &s->ovl)) != NCT_OK) return r;
+    const int nb = gram_chunks(s->S, 2 * s->N);
+    void* p = nullptr;
+    if ((r = dalloc(s, size_t(nb) * SS * 16, &p)) != NCT_OK) return r;
+    s->ovl_nb = nb;
+    s->ovl_part = p;
     return NCT_OK;
   }
 
@@ -1347,49 +1316,48 @@ struct Engine {
   // parts; states of different k are orthogonal through the Bloch factors).
   nct_status orthonormalize(const void* src, void* dst) {
     nct_status r;
-    if ((r = ensure_blas()) != NCT_OK) return r;
+    if ((r = ensure_ovl()) != NCT_OK) return r;
     std::vector<int> runs = s->has_k ? s->krun : std::vector<int>{0, s->S};
     for (size_t b = 0; b + 1 < runs.size(); ++b)
       if ((r = orthonormalize_run(src, dst, runs[b], runs[b + 1] - runs[b])) != NCT_OK) return r;
     return NCT_OK;
   }
 
+  // One run of S states starting at state i0: the overlap dV A^H A on the matrix cores with FP64
+  // accumulation (a split-K reduction over the 2N values of each state, summed in a fixed order),
+  // its Cholesky factorisation and L^-H on the host, and the triangular change of basis
+  // D_j = sum_{i <= j} A_i (L^-H)_ij on the matrix cores.
   nct_status orthonormalize_run(const void* src, void* dst, int i0, int S) {
-    using C = typename Blas<R>::C;
-    const rocblas_int K2 = rocblas_int(2 * s->N);
-    const C al(R(s->dV), R(0)), one(R(1), R(0)), zero(R(0), R(0));
-    const C* A0 = static_cast<const C*>(src) + size_t(i0) * K2;
-    C* D0 = static_cast<C*>(dst) + size_t(i0) * K2;
-    // overlap dV A^H A of this run: k = 2N is long and S x S small, so split K into nb strided
-    // chunks (one GEMM batch each), fold the remainder into chunk 0, and sum the partials with a
-    // GEMV
-    const rocblas_int nb = s->ovl_nb;
-    const rocblas_int kc = K2 / nb, krem = K2 - kc * nb;
-    const rocblas_stride SS = rocblas_stride(S) * S;
-    rocblas_status bs = Blas<R>::gemm_sb(s->blas, rocblas_operation_conjugate_transpose,
-                                         rocblas_operation_none, S, S, kc, &one, A0, K2, kc, A0, K2, kc,
-                                         &zero, s->ovl_part, S, SS, nb);
-    if (bs == rocblas_status_success && krem > 0)
-      bs = Blas<R>::gemm(s->blas, rocblas_operation_conjugate_transpose, rocblas_operation_none, S, S,
-                         krem, &one, A0 + size_t(kc) * nb, K2, A0 + size_t(kc) * nb, K2, &one,
-                         s->ovl_part, S);
-    if (bs == rocblas_status_success)
-      bs = Blas<R>::gemv(s->blas, rocblas_int(SS), nb, &al, s->ovl_part, rocblas_int(SS), s->ovl_ones,
-                         &zero, s->ovl);
-    if (bs != rocblas_status_success) return fail(s, NCT_ERR_HIP, "rocBLAS overlap: status %d", int(bs));
-    std::vector<cpx<R>> h(size_t(S) * S);
-    HIPCHK(s, hipMemcpyAsync(h.data(), s->ovl, h.size() * sizeof(cpx<R>), hipMemcpyDeviceToHost, s->st));
+    const size_t K2 = 2 * s->N;
+    const char* A0 = static_cast<const char*>(src) + size_t(i0) * K2 * sizeof(R) * 2;
+    char* D0 = static_cast<char*>(dst) + size_t(i0) * K2 * sizeof(R) * 2;
+    const int nb = std::min(s->ovl_nb, gram_chunks(S, K2));
+    // useful work: the S(S+1)/2 independent entries of the Hermitian overlap, 8 flops per
+    // complex multiply-add; algorithmic bytes: the run read once
+    const double gram_flops = 8.0 * K2 * double(S) * (S + 1) / 2;
+    nct_status r;
+    if ((r = check(timed(s, NCT_K_ORTH, double(S) * K2 * sizeof(R) * 2, gram_flops, [&] {
+           return launch_gram<R>(A0, S, K2, s->dV, s->ovl_part, nb, s->ovl, s->st); }), "overlap")) != NCT_OK)
+      return r;
+    const size_t SS = size_t(S) * S;
+    std::vector<std::complex<double>> h(SS);
+    HIPCHK(s, hipMemcpyAsync(h.data(), s->ovl, SS * 16, hipMemcpyDeviceToHost, s->st));
     HIPCHK(s, hipStreamSynchronize(s->st));
-    std::vector<std::complex<double>> A(h.size());
-    for (size_t k = 0; k < h.size(); ++k) A[k] = std::complex<double>(double(h[k].x), double(h[k].y));
+    // column-major copy for the factorisation (row-major [i][j] on the device)
+    std::vector<std::complex<double>> A(SS);
+    for (int i = 0; i < S; ++i)
+      for (int j = 0; j < S; ++j) A[size_t(i) + size_t(j) * S] = h[size_t(i) * S + j];
     if (!cholesky_inverse_h(A, S))
       return fail(s, NCT_ERR_NONFINITE, "overlap of the states is not positive definite");
-    for (size_t k = 0; k < h.size(); ++k) h[k] = cpx<R>{R(A[k].real()), R(A[k].imag())};
-    HIPCHK(s, hipMemcpyAsync(s->ovl, h.data(), h.size() * sizeof(cpx<R>), hipMemcpyHostToDevice, s->st));
-    bs = Blas<R>::gemm(s->blas, rocblas_operation_none, rocblas_operation_none, K2, S, S, &one, A0, K2,
-                       s->ovl, S, &zero, D0, K2);
-    if (bs != rocblas_status_success) return fail(s, NCT_ERR_HIP, "rocBLAS transform GEMM: status %d", int(bs));
-    HIPCHK(s, hipStreamSynchronize(s->st));  // h is released on return
+    s->ovl_host.resize(SS);
+    for (int i = 0; i < S; ++i)
+      for (int j = 0; j < S; ++j) s->ovl_host[size_t(i) * S + j] = A[size_t(i) + size_t(j) * S];
+    HIPCHK(s, hipMemcpyAsync(s->ovl, s->ovl_host.data(), SS * 16, hipMemcpyHostToDevice, s->st));
+    const double tflops = 8.0 * K2 * double(S) * (S + 1) / 2;
+    if ((r = check(timed(s, NCT_K_ORTH, 2.0 * K2 * S * sizeof(R) * 2 + SS * 16.0, tflops, [&] {
+           return launch_basis_transform<R>(A0, s->ovl, S, K2, D0, s->st); }), "basis transform")) != NCT_OK)
+      return r;
+    HIPCHK(s, hipStreamSynchronize(s->st));  // the factor's host copy is reused by the next run
     return NCT_OK;
   }
 
@@ -1536,10 +1504,6 @@ nct_status alloc_tape(nct_system* s, nct_system::Tape& T, int cap) {
 void free_all(nct_system* s) {
   for (hipStream_t q : {s->st2, s->stB, s->stB2})
     if (q) (void)hipStreamSynchronize(q);
-  if (s->blas) {
-    (void)rocblas_destroy_handle(s->blas);
-    s->blas = nullptr;
-  }
   for (auto& b : s->owned) (void)hipFree(b.p);
   s->owned.clear();
   for (hipEvent_t* e : {&s->ev_rows, &s->ev_proj, &s->evB_rows, &s->evB_proj, &s->ev_fork, &s->ev_join,
@@ -2011,6 +1975,13 @@ nct_status nct_backward_step(nct_system* s, int tape_index, const void* psi_n, d
   }
   for (int k = 0; k < 6; ++k)
     if (!std::isfinite(dB[k])) return fail(s, NCT_ERR_NONFINITE, "non-finite field gradient");
+  return NCT_OK;
+}
+
+nct_status nct_set_watchdog(nct_system* s, double max_rel_drift) {
+  if (!s) return NCT_ERR_ARG;
+  if (std::isnan(max_rel_drift)) return fail(s, NCT_ERR_ARG, "max_rel_drift is NaN");
+  s->max_ne_drift = max_rel_drift;
   return NCT_OK;
 }
 

@@ -121,8 +121,9 @@ constexpr int kFieldTot = 12;  // N_e, M_x, M_y, M_z, E_loc, E_H, E_xc, 0, D_x, 
 hipError_t launch_fields(const double* rho, const double* vext, const double* vH, int xc,
                          double thr, const int n[3], const double cell[3], double* fields,
                          float* fields32, double* part, int* nblk_out, hipStream_t st);
+// out[w] = sum_r part[r][w] (fixed order); copy0, if non-null, also receives out[0]
 hipError_t launch_reduce_rows(const double* part, int nrows, int width, double* out,
-                              hipStream_t st);
+                              hipStream_t st, double* copy0 = nullptr);
 // out = fields + {v_E, b}: v_E = lg[0] ix + lg[1] iy + lg[2] iz + lg[3] (laser), b added to b_xc
 hipError_t launch_add_bext(const double* fields, const int n[3], const double b[3],
                            const double lg[4], double* out, hipStream_t st);
@@ -187,6 +188,18 @@ LaunchEvents& launch_events();
 // {X, Y, Z position, charge, sigma, unused} and moments [natoms][3].
 hipError_t launch_dm_init(const int n[3], const double cell[3], int natoms, const double* atoms,
                           const double* moments, double* rho, hipStream_t st);
+
+// Orthonormalisation of a run of S states (rows of K = 2N complex values), FP64 arithmetic in
+// either precision.  launch_gram: out[S][S] = scale A^H A (Hermitian, both halves written) through
+// nchunks partial sums over K in part[nchunks][S][S] (complex double; gram_chunks() chooses
+// nchunks).  launch_basis_transform: D_j = sum_{i <= j} Mt[i][j] A_i with Mt [S][S] complex double
+// upper triangular (D and A distinct).
+int gram_chunks(int S, size_t K);
+template <typename R>
+hipError_t launch_gram(const void* A, int S, size_t K, double scale, void* part, int nchunks, void* out,
+                       hipStream_t st);
+template <typename R>
+hipError_t launch_basis_transform(const void* A, const void* Mt, int S, size_t K, void* D, hipStream_t st);
 
 bool plane_pair_supported(int ny, int nz);
 bool line_supported(int n);

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 
@@ -892,15 +893,19 @@ __global__ __launch_bounds__(256) void k_fields(const double* __restrict__ rho,
   }
 }
 
-// out[w] = sum_r part[r*width + w], fixed order
+// out[w] = sum_r part[r*width + w], fixed order; copy0, if given, receives out[0] as well
 __global__ __launch_bounds__(256) void k_reduce_rows(const double* __restrict__ part, int nrows,
-                                                     int width, double* __restrict__ out) {
+                                                     int width, double* __restrict__ out,
+                                                     double* __restrict__ copy0) {
   __shared__ double red[4];
   for (int w = 0; w < width; ++w) {
     double s = 0.0;
     for (int r = threadIdx.x; r < nrows; r += 256) s += part[size_t(r) * width + w];
     const double t = block_sum<256>(s, red);
-    if (threadIdx.x == 0) out[w] = t;
+    if (threadIdx.x == 0) {
+      out[w] = t;
+      if (w == 0 && copy0) *copy0 = t;
+    }
   }
 }
 
@@ -1386,6 +1391,159 @@ __global__ __launch_bounds__(256) void k_dm_init(int nx, int ny, int nz, double 
   rho[3 * N + p] = -n * my / 2.0;
 }
 
+// ---------------------------------------------------------------- orthonormalisation (ground state)
+// Overlap of a run of states and the triangular change of basis that orthonormalises them.  Both
+// are dense complex contractions on the matrix cores with FP64 operands and FP64 accumulation in
+// either precision (the overlap is a norm reduction over 2N terms).
+
+// Partial Gram matrices over K-chunks: part[c][i][j] = sum_{k in chunk c} conj(A[i][k]) A[j][k]
+// for the tile pairs (ti <= tj) of 32 x 32 state tiles; A is [S][K] (states are rows of K = 2N
+// complex values).  Four waves per workgroup, one 16 x 16 output tile each.
+constexpr int GRAM_T = 32;   // output tile (states)
+constexpr int GRAM_KB = 16;  // k values staged per iteration
+template <typename R>
+__global__ __launch_bounds__(256) void k_gram_partial(const cpx<R>* __restrict__ A, int S, size_t K,
+                                                      size_t kchunk, cpx<double>* __restrict__ part) {
+  using M = mfma16<double>;
+  __shared__ cpx<double> sa[GRAM_T][GRAM_KB + 1];
+  __shared__ cpx<double> sb[GRAM_T][GRAM_KB + 1];
+  const int T = (S + GRAM_T - 1) / GRAM_T;
+  int pidx = blockIdx.x, ti = 0;
+  while (pidx >= T - ti) {
+    pidx -= T - ti;
+    ++ti;
+  }
+  const int tj = ti + pidx;
+  const size_t k0 = size_t(blockIdx.y) * kchunk;
+  const size_t k1 = min(K, k0 + kchunk);
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int wi = w >> 1, wj = w & 1;
+  const int c = lane & 15, kl = lane >> 4;
+  M::acc cr = M::zero(), ci = M::zero();
+  for (size_t kb = k0; kb < k1; kb += GRAM_KB) {
+#pragma unroll
+    for (int e = tid; e < GRAM_T * GRAM_KB; e += 256) {
+      const int r = e / GRAM_KB, kk = e % GRAM_KB;
+      const size_t k = kb + kk;
+      const int ri = ti * GRAM_T + r, rj = tj * GRAM_T + r;
+      cpx<double> va = {0.0, 0.0}, vb = {0.0, 0.0};
+      if (k < k1 && ri < S) {
+        const cpx<R> v = A[size_t(ri) * K + k];
+        va = {double(v.x), double(v.y)};
+      }
+      if (k < k1 && rj < S) {
+        const cpx<R> v = A[size_t(rj) * K + k];
+        vb = {double(v.x), double(v.y)};
+      }
+      sa[r][kk] = va;
+      sb[r][kk] = vb;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < GRAM_KB; ks += 4) {
+      const cpx<double> a = sa[wi * 16 + c][ks + kl];  // A operand: row i, column k
+      const cpx<double> b = sb[wj * 16 + c][ks + kl];  // B operand: row k, column j
+      cr = M::op(a.x, b.x, cr);
+      cr = M::op(a.y, b.y, cr);
+      ci = M::op(a.x, b.y, ci);
+      ci = M::op(-a.y, b.x, ci);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = ti * GRAM_T + wi * 16 + M::row(r, kl);
+    const int j = tj * GRAM_T + wj * 16 + c;
+    if (i < S && j < S) part[(size_t(blockIdx.y) * S + i) * S + j] = {cr[r], ci[r]};
+  }
+}
+
+// out[i][j] = scale sum_c part[c][i][j] (chunk order) for j >= i, and its conjugate at [j][i].
+__global__ __launch_bounds__(256) void k_gram_reduce(const cpx<double>* __restrict__ part, int S, int nchunks,
+                                                     double scale, cpx<double>* __restrict__ out) {
+  const size_t idx = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= size_t(S) * S) return;
+  const int i = int(idx / S), j = int(idx - size_t(i) * S);
+  if (j < i) return;
+  double sr = 0.0, si = 0.0;
+  for (int cch = 0; cch < nchunks; ++cch) {
+    const cpx<double> v = part[(size_t(cch) * S + i) * S + j];
+    sr += v.x;
+    si += v.y;
+  }
+  out[size_t(i) * S + j] = {scale * sr, scale * si};
+  if (j != i) out[size_t(j) * S + i] = {scale * sr, -scale * si};
+}
+
+// D[j][p] = sum_{i <= j} Mt[i][j] A[i][p] (Mt upper triangular, FP64): the states D_j = sum_i
+// A_i M_ij.  One workgroup: 64 states j x 64 columns p; wave w owns states w*16 .. w*16+15 and
+// four 16-column MFMA tiles.  Only i below the tile's last j contribute.
+constexpr int BT_J = 64;
+constexpr int BT_P = 64;
+constexpr int BT_KI = 16;
+template <typename R>
+__global__ __launch_bounds__(256) void k_basis_transform(const cpx<R>* __restrict__ A,
+                                                         const cpx<double>* __restrict__ Mt, int S,
+                                                         size_t K, cpx<R>* __restrict__ D) {
+  using M = mfma16<double>;
+  __shared__ cpx<double> sm[BT_J][BT_KI + 1];   // [j][i]
+  __shared__ cpx<double> sx[BT_KI][BT_P + 1];   // [i][p]
+  const int j0 = blockIdx.y * BT_J;
+  const size_t p0 = size_t(blockIdx.x) * BT_P;
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int c = lane & 15, kl = lane >> 4;
+  M::acc dr[4], di[4];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    dr[h] = M::zero();
+    di[h] = M::zero();
+  }
+  const int iend = min(S, j0 + BT_J);
+  for (int i0 = 0; i0 < iend; i0 += BT_KI) {
+#pragma unroll
+    for (int e = tid; e < BT_KI * BT_J; e += 256) {
+      const int il = e / BT_J, jl = e % BT_J;
+      const int i = i0 + il, j = j0 + jl;
+      sm[jl][il] = (i < S && j < S) ? Mt[size_t(i) * S + j] : cpx<double>{0.0, 0.0};
+    }
+#pragma unroll
+    for (int e = tid; e < BT_KI * BT_P; e += 256) {
+      const int il = e / BT_P, pl = e % BT_P;
+      const int i = i0 + il;
+      const size_t pp = p0 + pl;
+      cpx<double> v = {0.0, 0.0};
+      if (i < S && pp < K) {
+        const cpx<R> a = A[size_t(i) * K + pp];
+        v = {double(a.x), double(a.y)};
+      }
+      sx[il][pl] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < BT_KI; ks += 4) {
+      const cpx<double> a = sm[w * 16 + c][ks + kl];  // A operand: row j, column i
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const cpx<double> b = sx[ks + kl][h * 16 + c];  // B operand: row i, column p
+        dr[h] = M::op(a.x, b.x, dr[h]);
+        dr[h] = M::op(-a.y, b.y, dr[h]);
+        di[h] = M::op(a.x, b.y, di[h]);
+        di[h] = M::op(a.y, b.x, di[h]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = j0 + w * 16 + M::row(r, kl);
+      const size_t pp = p0 + h * 16 + c;
+      if (j < S && pp < K) D[size_t(j) * K + pp] = {R(dr[h][r]), R(di[h][r])};
+    }
+  }
+}
+
 // ================================================================ launchers
 static inline unsigned nblocks(size_t n, unsigned bs) { return unsigned((n + bs - 1) / bs); }
 
@@ -1638,8 +1796,8 @@ hipError_t launch_fields(const double* rho, const double* vext, const double* vH
 }
 
 hipError_t launch_reduce_rows(const double* part, int nrows, int width, double* out,
-                              hipStream_t st) {
-  nct_launch(k_reduce_rows, dim3(1), dim3(256), 0, st, part, nrows, width, out);
+                              hipStream_t st, double* copy0) {
+  nct_launch(k_reduce_rows, dim3(1), dim3(256), 0, st, part, nrows, width, out, copy0);
   return hipGetLastError();
 }
 hipError_t launch_add_bext(const double* fields, const int n[3], const double b[3],
@@ -1687,6 +1845,43 @@ hipError_t launch_proj_scatter(const ProjTables& pt, const void* EC, int S, void
   else
     nct_launch((k_proj_scatter<R, 32>), grid, dim3(64), 0, st, pt,
                        reinterpret_cast<const cpx<R>*>(EC), S, reinterpret_cast<cpx<R>*>(Y));
+  return hipGetLastError();
+}
+
+int gram_chunks(int S, size_t K) {
+  const int T = (S + GRAM_T - 1) / GRAM_T;
+  const size_t pairs = size_t(T) * (T + 1) / 2;
+  size_t nc = (2048 + pairs - 1) / pairs;                              // enough workgroups
+  nc = std::min<size_t>(nc, 256);
+  nc = std::min<size_t>(nc, std::max<size_t>(1, (size_t(64) << 20) / (size_t(S) * S * 16)));  // partials <= 64 MiB
+  nc = std::min<size_t>(nc, std::max<size_t>(1, K / (4 * GRAM_KB)));   // chunks of >= 64 values
+  return int(std::max<size_t>(nc, 1));
+}
+
+template <typename R>
+hipError_t launch_gram(const void* A, int S, size_t K, double scale, void* part, int nchunks, void* out,
+                       hipStream_t st) {
+  if (S <= 0 || nchunks <= 0) return hipErrorInvalidValue;
+  const int T = (S + GRAM_T - 1) / GRAM_T;
+  const unsigned pairs = unsigned(T) * unsigned(T + 1) / 2;
+  size_t kchunk = (K + nchunks - 1) / nchunks;
+  kchunk = (kchunk + GRAM_KB - 1) / GRAM_KB * GRAM_KB;
+  const unsigned used = unsigned((K + kchunk - 1) / kchunk);
+  nct_launch((k_gram_partial<R>), dim3(pairs, used), dim3(256), 0, st, reinterpret_cast<const cpx<R>*>(A), S, K,
+             kchunk, reinterpret_cast<cpx<double>*>(part));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  nct_launch(k_gram_reduce, dim3(nblocks(size_t(S) * S, 256)), dim3(256), 0, st,
+             reinterpret_cast<const cpx<double>*>(part), S, int(used), scale, reinterpret_cast<cpx<double>*>(out));
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_basis_transform(const void* A, const void* Mt, int S, size_t K, void* D, hipStream_t st) {
+  if (S <= 0) return hipErrorInvalidValue;
+  const dim3 grid(unsigned((K + BT_P - 1) / BT_P), unsigned((S + BT_J - 1) / BT_J));
+  nct_launch((k_basis_transform<R>), grid, dim3(256), 0, st, reinterpret_cast<const cpx<R>*>(A),
+             reinterpret_cast<const cpx<double>*>(Mt), S, K, reinterpret_cast<cpx<R>*>(D));
   return hipGetLastError();
 }
 
@@ -1764,7 +1959,9 @@ hipError_t launch_density_backprop(const void* psi, const double* occ, const dou
   template hipError_t launch_pair<R>(const void*, const void*, int, size_t, double, double*,      \
                                      hipStream_t);                                               \
   template hipError_t launch_density_backprop<R>(const void*, const double*, const double*, int,  \
-                                                 size_t, int, void*, hipStream_t);
+                                                 size_t, int, void*, hipStream_t);               \
+  template hipError_t launch_gram<R>(const void*, int, size_t, double, void*, int, void*, hipStream_t); \
+  template hipError_t launch_basis_transform<R>(const void*, const void*, int, size_t, void*, hipStream_t);
 NCT_INST(double)
 NCT_INST(float)
 

@@ -32,9 +32,13 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
+import scipy.fft as sfft
+import scipy.linalg
 
 SEED_BASE = 21908
 
@@ -168,27 +172,58 @@ def gaussian_local_potential(n, L, positions, depths, widths) -> np.ndarray:
     return v
 
 
+def _workers() -> int:
+    """Host threads for input generation (the cores this process may run on)."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:  # pragma: no cover - non-Linux hosts
+        return max(1, os.cpu_count() or 1)
+
+
 def _smooth_noise(rng, count: int, n, L, sigma: float = 1.0) -> np.ndarray:
-    """Complex normal noise on the grid, smoothed by exp(-|G|^2 sigma^2/2)."""
-    shape = (count,) + tuple(n)
-    z = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    """Complex normal noise on the grid, smoothed by exp(-|G|^2 sigma^2/2).
+
+    Row i draws its 2N normals (interleaved real and imaginary parts) from its own child generator
+    rng.spawn(count)[i], so rows can be drawn on several threads with a result that does not
+    depend on the thread count."""
+    N = int(np.prod(n))
+    z = np.empty((count, N), dtype=np.complex128)
+    zr = z.view(np.float64)                       # [count, 2N]: re, im, re, im, ...
+    kids = rng.spawn(count)
+
+    def draw(i):
+        kids[i].standard_normal(out=zr[i])
+
+    with ThreadPoolExecutor(max_workers=_workers()) as ex:
+        list(ex.map(draw, range(count)))
+    z = z.reshape((count,) + tuple(n))
     g2 = np.zeros(tuple(n))
     for d in range(3):
         g = 2.0 * np.pi * np.fft.fftfreq(n[d], d=L[d] / n[d])
         sh = [1, 1, 1]
         sh[d] = n[d]
         g2 = g2 + (g ** 2).reshape(sh)
-    zf = np.fft.fftn(z, axes=(-3, -2, -1)) * np.exp(-0.5 * g2 * sigma * sigma)
-    return np.fft.ifftn(zf, axes=(-3, -2, -1))
+    filt = np.exp(-0.5 * g2 * sigma * sigma)
+    w = _workers()
+    z = sfft.fftn(z, axes=(-3, -2, -1), workers=w, overwrite_x=True)
+    z *= filt
+    return sfft.ifftn(z, axes=(-3, -2, -1), workers=w, overwrite_x=True)
 
 
 def _orthonormal_columns(vecs: np.ndarray, dV: float) -> np.ndarray:
-    """Orthonormalise rows of vecs [count, M] under <a|b> = dV sum a* b (FP64 QR)."""
-    q, r = np.linalg.qr(vecs.T)
-    # fix the phase convention so the result does not depend on LAPACK's sign choices
-    ph = np.diag(r) / np.abs(np.diag(r))
-    q = q * ph[None, :]
-    return (q.T / math.sqrt(dV)).copy()
+    """Orthonormalise the rows of vecs [count, M] under <a|b> = dV sum a* b in FP64.
+
+    Cholesky QR applied twice (Fukaya, Nakatsukasa, Yanagisawa and Yamamoto, "CholeskyQR2",
+    2014): with G = dV conj(Z) Z^T = L L^H, the rows of conj(L)^-1 Z are orthonormal; the
+    second pass removes the rounding left by the first.  The Cholesky factor has a positive
+    real diagonal, so the result is unique (no sign or phase convention of a library)."""
+    q = np.ascontiguousarray(vecs, dtype=np.complex128)
+    for _ in range(2):
+        G = dV * (q.conj() @ q.T)
+        Lc = scipy.linalg.cholesky(G, lower=True)
+        q = scipy.linalg.solve_triangular(Lc.conj(), q, lower=True, overwrite_b=True,
+                                          check_finite=False)
+    return q
 
 
 def random_spinors_full(rng, S: int, n, L) -> np.ndarray:
@@ -393,8 +428,23 @@ def workload(case: int) -> Workload:
       envelope (sigma 3.5 bohr) about the centre, z-polarised electric pulse A = 1 a.u.,
       omega = 10 eV, t0 = 0.1 fs, tau = 0.5 fs (the parameters of the paper's cluster runs),
       200 steps
+    7 reduced system that keeps every term of the step, for long trajectories against the oracle:
+      16^3 grid (h = 0.42 bohr, L = 6.72), 8 spinor states tilted as in cases 1-4, 2 atoms x 18
+      KB+SOC projectors (minimum-image separation >= 4 bohr), Gaussian local potential, exchange
+      + Hartree, the circular pulse of case 2 (A = 0.005, omega = 0.5, t0 = 25, tau = 5), 1000
+      steps of dt = 0.05 (the pulse's whole envelope)
     """
     r_pos, r_depth, r_states, _r_jit = _rngs(case)
+    if case == 7:
+        n, L, S, natoms = (16, 16, 16), (6.72,) * 3, 8, 2
+        pos = separated_positions(r_pos, natoms, L, 4.0)
+        depths = r_depth.uniform(1.0, 3.0, natoms)
+        widths = np.ones(natoms)
+        v_ext = gaussian_local_potential(n, L, pos, depths, widths)
+        psi0 = tilted_product_spinors(r_states, S, n, L)
+        bf = BField(pulses=[Pulse(A=0.005, omega=0.5, t0=25.0, tau=5.0)])
+        return Workload("reduced-16^3x8-2x18KB-pulse", n, L, S, np.ones(S), pos, depths, widths,
+                        v_ext, kb_channels(), 2.5, psi0, bf, 0.05, 1000)
     if case == 6:
         w = workload(2)
         nk, per = 8, 32

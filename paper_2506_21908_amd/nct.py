@@ -21,7 +21,8 @@ NCT_GAUGE_LENGTH, NCT_GAUGE_VELOCITY = 0, 1
 NCT_FP64, NCT_FP32_MIXED = 0, 1
 STATUS_NAMES = {0: "NCT_OK", 1: "NCT_ERR_ARG", 2: "NCT_ERR_UNSUPPORTED", 3: "NCT_ERR_OOM",
                 4: "NCT_ERR_HIP", 5: "NCT_ERR_NONFINITE", 6: "NCT_ERR_STATE"}
-KERNEL_CLASSES = ["plane_stage", "xpass", "plane_fwd", "density", "fields", "proj", "obs", "adjoint"]
+KERNEL_CLASSES = ["plane_stage", "xpass", "plane_fwd", "density", "fields", "proj", "obs", "adjoint",
+                  "orth"]
 OBS_NAMES = ["t", "N_e", "M_x", "M_y", "M_z", "E_total", "E_kin", "E_loc", "E_NL", "E_H",
              "E_xc", "E_Z", "max_norm_err"]
 
@@ -105,6 +106,8 @@ def lib():
         L.nct_backward_step.argtypes = [c_void_p, c_int, c_void_p, c_double, c_void_p, c_void_p,
                                         POINTER(c_double), POINTER(c_double)]
         L.nct_backward_step.restype = c_int
+        L.nct_set_watchdog.argtypes = [c_void_p, c_double]
+        L.nct_set_watchdog.restype = c_int
         L.nct_set_timing.argtypes = [c_void_p, c_int]
         L.nct_set_timing.restype = c_int
         L.nct_set_timing_sample.argtypes = [c_void_p, c_int]
@@ -189,6 +192,7 @@ class System:
         self.precision = int(precision)
         self.dtype = torch.complex128 if precision == NCT_FP64 else torch.complex64
         self.npulses = 0
+        self.bfield_args = ((0.0, 0.0, 0.0), [])  # (B0, pulses) last given to set_potentials
 
     # ------------------------------------------------------------------ helpers
     def _check(self, rc: int):
@@ -219,10 +223,11 @@ class System:
             for k, q in enumerate(pl):
                 arr[k] = Pulse(q.A, q.omega, q.t0, q.tau, getattr(q, "phase", 0.0),
                                (c_double * 3)(*q.e1), (c_double * 3)(*q.e2))
-            bf = BField((c_double * 3)(*(B0 if B0 is not None else (0.0, 0.0, 0.0))), len(pl),
-                        ctypes.cast(arr, POINTER(Pulse)) if pl else None)
+            b0 = tuple(float(v) for v in (B0 if B0 is not None else (0.0, 0.0, 0.0)))
+            bf = BField((c_double * 3)(*b0), len(pl), ctypes.cast(arr, POINTER(Pulse)) if pl else None)
             self._keep.append(arr)
             self.npulses = len(pl)
+            self.bfield_args = (b0, list(pl))
         self._check(lib().nct_set_potentials(self.h, _tptr(v_ext),
                                              ctypes.byref(bf) if bf is not None else None,
                                              _tptr(fields)))
@@ -296,6 +301,10 @@ class System:
                                             _dptr(dLdtheta) if dLdtheta is not None else None))
         return dLdB
 
+    def set_watchdog(self, max_rel_drift: float):
+        """Largest relative drift of N_e over one nct_step call (<= 0: finiteness only)."""
+        self._check(lib().nct_set_watchdog(self.h, float(max_rel_drift)))
+
     def set_timing(self, mask: int):
         """Bit k of mask instruments kernel class k (KERNEL_CLASSES); -1 = all, 0 = off."""
         self._check(lib().nct_set_timing(self.h, int(mask)))
@@ -368,6 +377,9 @@ def _make_pulse_mz():
         (nct_magnetization_seed), then for each segment in reverse re-runs it with the tape on
         (nct_step(tape=1)) and calls nct_backward_step step by step; the library adds
         dL/dB . dB/dtheta into the gradient.  The system's tape_steps must be >= checkpoint_every.
+        backward re-applies the field of its own forward call (theta and B0 are kept in ctx), so
+        other forward calls on the same system in between (finite differences, line searches)
+        do not change the gradient; the field the system held before backward is restored.
         """
 
         @staticmethod
@@ -391,20 +403,26 @@ def _make_pulse_mz():
             ctx.ckpts = ckpts
             ctx.psi_final = psi
             ctx.npar = 2 * len(pulses)
+            ctx.field = (tuple(float(v) for v in B0), _pulses_with(pulses, th))
             return torch.tensor(float(tot[3]), dtype=torch.float64)
 
         @staticmethod
         def backward(ctx, gout):
             s = ctx.system
             dt = float(s.params.dt)
-            lam = torch.empty_like(ctx.psi_final)
-            s.magnetization_seed(ctx.psi_final, (0.0, 0.0, 1.0), lam)
-            grad = np.zeros(ctx.npar)
-            for psi_c, t_c, n in reversed(ctx.ckpts):
-                psi = psi_c.clone()
-                s.step(psi, t_c, n, tape=True)
-                for j in reversed(range(n)):
-                    s.backward_step(j, None, t_c + j * dt, lam, lam, grad)
+            held = s.bfield_args
+            s.set_potentials(B0=ctx.field[0], pulses=ctx.field[1])
+            try:
+                lam = torch.empty_like(ctx.psi_final)
+                s.magnetization_seed(ctx.psi_final, (0.0, 0.0, 1.0), lam)
+                grad = np.zeros(ctx.npar)
+                for psi_c, t_c, n in reversed(ctx.ckpts):
+                    psi = psi_c.clone()
+                    s.step(psi, t_c, n, tape=True)
+                    for j in reversed(range(n)):
+                        s.backward_step(j, None, t_c + j * dt, lam, lam, grad)
+            finally:
+                s.set_potentials(B0=held[0], pulses=held[1])
             g = torch.from_numpy(grad * float(gout))
             return g, None, None, None, None, None, None, None
 

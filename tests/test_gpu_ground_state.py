@@ -8,6 +8,7 @@ import pytest
 
 from oracle import nct_oracle as O
 from paper_2506_21908_amd import inputs as I
+from parity_metrics import max_rel, nm_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -77,10 +78,9 @@ def test_ground_state_vs_oracle(torch_cuda, prec):
     say(f"  E oracle {E_ref[0]:.12f} .. {E_ref[-1]:.12f}   gpu {E[0]:.12f} .. {E[-1]:.12f}")
     tol = 1e-10 if prec == "fp64" else 1e-5
     assert np.max(np.abs(E - E_ref)) < tol * np.max(np.abs(E_ref))
-    na, ma = O.charge_and_magnetization(O.spin_density(psi.cpu().numpy().astype(np.complex128), sysd.occ))
-    nb, mb = O.charge_and_magnetization(O.spin_density(psi_ref, sysd.occ))
-    assert np.linalg.norm(na - nb) / np.linalg.norm(nb) < tol
-    assert np.linalg.norm(ma - mb) / np.linalg.norm(nb) < tol
+    en, em, _, _ = nm_errors(psi.cpu().numpy().astype(np.complex128), psi_ref, sysd.occ)
+    say(f"  n, m max-abs {en:.2e} {em:.2e}")
+    assert en < tol and em < tol
     assert E[-1] < E[0]
 
 

@@ -8,6 +8,7 @@ import pytest
 
 from oracle import nct_oracle as O
 from paper_2506_21908_amd import inputs as I
+from parity_metrics import max_rel, nm_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -33,10 +34,7 @@ def _errors(obs, ref, psi, psi_ref, occ):
     e_N = np.max(np.abs(obs[:, 1] - ref[:, 1])) / abs(ref[0, 1])
     e_M = np.max(np.abs(obs[:, 2:5] - ref[:, 2:5])) / max(np.max(np.abs(ref[:, 2:5])), 1.0)
     e_E = np.max(np.abs(obs[:, 5:12] - ref[:, 5:12])) / max(np.max(np.abs(ref[:, 5:12])), 1.0)
-    na, ma = O.charge_and_magnetization(O.spin_density(psi, occ))
-    nb, mb = O.charge_and_magnetization(O.spin_density(psi_ref, occ))
-    en = np.linalg.norm(na - nb) / np.linalg.norm(nb)
-    em = np.linalg.norm(ma - mb) / np.linalg.norm(nb)
+    en, em, _, _ = nm_errors(psi, psi_ref, occ)  # point by point over the grid
     return e_N, e_M, e_E, en, em
 
 
@@ -94,6 +92,7 @@ def test_lsda_cluster_workload_one_step_vs_oracle(torch_cuda):
     s = nct.system_from_workload(w)
     psi = nct.states_to_device(w.psi0)
     obs = s.step(psi, 0.0, 1, obs=True)
-    errs = _errors(obs, obs_ref[1:], psi.cpu().numpy(), psi_ref, sysd.occ)
-    say("  N_e %.2e M %.2e E %.2e n %.2e m %.2e" % errs)
+    got = psi.cpu().numpy()
+    errs = _errors(obs, obs_ref[1:], got, psi_ref, sysd.occ) + (max_rel(got, psi_ref),)
+    say("  N_e %.2e M %.2e E %.2e n %.2e m %.2e psi %.2e (max-abs)" % errs)
     assert max(errs) < 1e-10

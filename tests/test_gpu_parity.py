@@ -11,6 +11,7 @@ import pytest
 
 from oracle import nct_oracle as O
 from paper_2506_21908_amd import inputs as I
+from parity_metrics import max_rel, nm_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -152,12 +153,9 @@ def _compare_traj(obs_gpu, obs_ref, tol):
 
 
 def _final_nm_errors(psi_gpu, psi_ref, occ):
-    rg = O.spin_density(psi_gpu, occ)
-    rr = O.spin_density(psi_ref, occ)
-    ng, mg = O.charge_and_magnetization(rg)
-    nr, mr = O.charge_and_magnetization(rr)
-    en = np.linalg.norm(ng - nr) / np.linalg.norm(nr)
-    em = np.linalg.norm(mg - mr) / np.linalg.norm(nr)
+    """Point by point: max |dn| / max n and max |dm| / max n over the grid."""
+    en, em, l2n, l2m = nm_errors(psi_gpu, psi_ref, occ)
+    say(f"  n, m max-abs {en:.2e} {em:.2e} (L2 {l2n:.2e} {l2m:.2e})")
     return en, em
 
 
@@ -219,9 +217,11 @@ def test_step_cluster_workload_fp64_one_step(torch_cuda):
     psi = nct.states_to_device(w.psi0)
     obs = s.step(psi, 0.0, 1, obs=True)
     _compare_traj(obs, obs_ref[1:], 1e-10)
-    en, em = _final_nm_errors(psi.cpu().numpy(), psi_ref, sysd.occ)
-    say(f"  final n {en:.2e} m {em:.2e}")
-    assert en < 1e-10 and em < 1e-10
+    got = psi.cpu().numpy()
+    en, em = _final_nm_errors(got, psi_ref, sysd.occ)
+    ep = max_rel(got, psi_ref)
+    say(f"  final n {en:.2e} m {em:.2e} psi {ep:.2e} (max-abs)")
+    assert en < 1e-10 and em < 1e-10 and ep < 1e-10
 
 
 def test_step_overlap_groups_bitwise(torch_cuda):
@@ -414,3 +414,25 @@ def test_nonfinite_detected(torch_cuda):
     with pytest.raises(nct.NctError) as e:
         s.step(psi, 0.0, 1)
     assert e.value.code == nct.NCT_ERR_NONFINITE
+
+
+def test_watchdog_stops_unstable_propagation(torch_cuda):
+    """A time step far outside the Taylor polynomial's stability range (x = E_max dt / 2 ~ 6.6
+    against 2.83 for K = 4) makes the norm grow from the first steps: nct_step reports
+    NCT_ERR_NONFINITE naming the step at which the electron count left its bound; with the bound
+    lifted (finiteness only) the same call succeeds as long as the numbers stay finite."""
+    nct = nct_mod()
+    say("watchdog: unstable time step")
+    w = I.make_system(n=(8, 8, 8), L=(6.0,) * 3, nstates=2, case=33, dt=0.5)
+    s = nct.system_from_workload(w)
+    psi = nct.states_to_device(w.psi0)
+    with pytest.raises(nct.NctError) as e:
+        s.step(psi, 0.0, 6)
+    assert e.value.code == nct.NCT_ERR_NONFINITE
+    assert "step" in str(e.value) and "drifted" in str(e.value)
+    s.set_watchdog(0.0)
+    psi = nct.states_to_device(w.psi0)
+    s.step(psi, 0.0, 1)
+    with pytest.raises(nct.NctError) as e:
+        s.set_watchdog(float("nan"))
+    assert e.value.code == nct.NCT_ERR_ARG

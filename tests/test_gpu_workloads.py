@@ -16,6 +16,7 @@ import pytest
 
 from oracle import nct_oracle as O
 from paper_2506_21908_amd import inputs as I
+from parity_metrics import max_rel, nm_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -55,10 +56,10 @@ def _traj_errors(obs, ref):
 
 
 def _nm_errors(psi_a, psi_b, occ):
-    ra, rb = O.spin_density(psi_a, occ), O.spin_density(psi_b, occ)
-    na, ma = O.charge_and_magnetization(ra)
-    nb, mb = O.charge_and_magnetization(rb)
-    return (np.linalg.norm(na - nb) / np.linalg.norm(nb), np.linalg.norm(ma - mb) / np.linalg.norm(nb))
+    """Point by point: max |dn| / max n and max |dm| / max n over the grid."""
+    en, em, l2n, l2m = nm_errors(psi_a, psi_b, occ)
+    say(f"  n, m max-abs {en:.2e} {em:.2e} (L2 {l2n:.2e} {l2m:.2e})")
+    return en, em
 
 
 def test_solid_workload_fp64_one_step_vs_oracle(torch_cuda, solid):
@@ -73,9 +74,11 @@ def test_solid_workload_fp64_one_step_vs_oracle(torch_cuda, solid):
     psi = nct.states_to_device(w.psi0)
     obs = s.step(psi, 0.0, 1, obs=True)
     e_N, e_M, e_E = _traj_errors(obs, obs_ref[1:])
-    en, em = _nm_errors(psi.cpu().numpy(), psi_ref, sysd.occ)
-    say(f"  N_e {e_N:.2e} M {e_M:.2e} E {e_E:.2e} n {en:.2e} m {em:.2e}")
-    assert max(e_N, e_M, e_E, en, em) < 1e-10
+    got = psi.cpu().numpy()
+    en, em = _nm_errors(got, psi_ref, sysd.occ)
+    ep = max_rel(got, psi_ref)
+    say(f"  N_e {e_N:.2e} M {e_M:.2e} E {e_E:.2e} n {en:.2e} m {em:.2e} psi {ep:.2e}")
+    assert max(e_N, e_M, e_E, en, em, ep) < 1e-10
 
 
 def test_solid_workload_mixed_vs_fp64_1000_steps(torch_cuda, solid):
