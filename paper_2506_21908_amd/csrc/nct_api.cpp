@@ -17,8 +17,10 @@
 #include "../../include/nct.h"
 #include "nct_fft.hpp"
 #include "nct_internal.hpp"
+#include "nct_tables.hpp"
 
 using namespace nct;
+using nct::tables::gl24;
 
 namespace {
 
@@ -309,98 +311,8 @@ double gval(int k, int Nl, double Lc) {
   return 2.0 * kPi * ks / Lc;
 }
 
-// ---------------------------------------------------------------- spherical harmonics
-std::complex<double> ylm(int l, int m, double x, double y, double z) {
-  using C = std::complex<double>;
-  if (std::abs(m) > l) return C(0, 0);
-  const double pi = kPi;
-  if (l == 0) return C(0.5 / std::sqrt(pi), 0);
-  if (l == 1) {
-    if (m == 0) return C(std::sqrt(3.0 / (4 * pi)) * z, 0);
-    return -double(m) * std::sqrt(3.0 / (8 * pi)) * C(x, m * y);
-  }
-  if (l == 2) {
-    if (m == 0) return C(std::sqrt(5.0 / (16 * pi)) * (3 * z * z - 1), 0);
-    if (std::abs(m) == 1) return -double(m) * std::sqrt(15.0 / (8 * pi)) * z * C(x, m * y);
-    const double sgn = m > 0 ? 1.0 : -1.0;
-    const C u(x, sgn * y);
-    return std::sqrt(15.0 / (32 * pi)) * u * u;
-  }
-  return C(0, 0);
-}
-
-// Gauss-Legendre nodes/weights on [-1,1]
-void gauss_legendre(int n, std::vector<double>& xs, std::vector<double>& ws) {
-  xs.assign(n, 0);
-  ws.assign(n, 0);
-  for (int i = 0; i < (n + 1) / 2; ++i) {
-    double x = std::cos(kPi * (i + 0.75) / (n + 0.5));
-    for (int it = 0; it < 100; ++it) {
-      double p0 = 1, p1 = x;
-      for (int k = 2; k <= n; ++k) {
-        double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
-        p0 = p1;
-        p1 = p2;
-      }
-      const double dp = n * (x * p1 - p0) / (x * x - 1);
-      const double dx = p1 / dp;
-      x -= dx;
-      if (std::fabs(dx) < 1e-16) break;
-    }
-    double p0 = 1, p1 = x;
-    for (int k = 2; k <= n; ++k) {
-      double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
-      p0 = p1;
-      p1 = p2;
-    }
-    const double dp = n * (x * p1 - p0) / (x * x - 1);
-    xs[i] = -x;
-    xs[n - 1 - i] = x;
-    ws[i] = ws[n - 1 - i] = 2.0 / ((1 - x * x) * dp * dp);
-  }
-}
-
-// 24-point Gauss-Legendre rule on [-1, 1], built once (thread-safe static initialisation)
-struct GLRule {
-  std::vector<double> x, w;
-  explicit GLRule(int n) { gauss_legendre(n, x, w); }
-};
-const GLRule& gl24() {
-  static const GLRule rule(24);
-  return rule;
-}
-
-// sqrt( int_0^rs (r^l e^{-r^2/2rc^2})^2 r^2 dr ), composite Gauss-Legendre
-double radial_norm(int l, double rc, double rs) {
-  const std::vector<double>& xs = gl24().x;
-  const std::vector<double>& ws = gl24().w;
-  const int panels = 16;
-  double acc = 0.0;
-  for (int p = 0; p < panels; ++p) {
-    const double a = rs * p / panels, b = rs * (p + 1) / panels;
-    for (size_t q = 0; q < xs.size(); ++q) {
-      const double r = 0.5 * (a + b) + 0.5 * (b - a) * xs[q];
-      const double f = std::pow(r, l) * std::exp(-r * r / (2 * rc * rc));
-      acc += 0.5 * (b - a) * ws[q] * f * f * r * r;
-    }
-  }
-  return std::sqrt(acc);
-}
-
-// Spinor harmonic coefficients: Phi = c_up Y_l^{m_up} chi_up + c_dn Y_l^{m_dn} chi_dn
-void spinor_coeffs(int l, int twoj, int twomj, double& cu, int& mu, double& cd, int& md) {
-  const double mj = 0.5 * twomj;
-  mu = (twomj - 1) / 2;  // twomj is odd: exact division, m_up = m_j - 1/2
-  md = (twomj + 1) / 2;  // m_dn = m_j + 1/2
-  if (twoj == 2 * l + 1) {
-    cu = std::sqrt((l + mj + 0.5) / (2 * l + 1));
-    cd = std::sqrt((l - mj + 0.5) / (2 * l + 1));
-  } else {
-    cu = std::sqrt((l - mj + 0.5) / (2 * l + 1));
-    cd = -std::sqrt((l + mj + 0.5) / (2 * l + 1));
-  }
-}
-
+// Projector tables: built on the host (nct_tables.hpp), converted to the system's precision and
+// uploaded.
 template <typename R>
 nct_status build_projectors(nct_system* s) {
   const nct_params& p = s->prm;
@@ -409,101 +321,33 @@ nct_status build_projectors(nct_system* s) {
   int P = 0;
   for (int c = 0; c < p.nchannels; ++c) P += p.channels[c].twoj + 1;
   if (P > 32) return fail(s, NCT_ERR_UNSUPPORTED, "at most 32 projectors per atom (got %d)", P);
-  const int PP = ((P + 15) / 16) * 16;
-  const int NX = s->n[0], NY = s->n[1], NZ = s->n[2];
-  const double h[3] = {p.cell[0] / NX, p.cell[1] / NY, p.cell[2] / NZ};
-  const double rs = p.r_sphere;
-  std::vector<int> row_off(s->natoms + 1, 0);
-  std::vector<int> pidx;
-  std::vector<int> ix_of_row;
-  std::vector<std::complex<double>> beta;  // [J][2][PP]
-  std::vector<R> disp;                      // [J][3]
-  std::vector<double> energy(size_t(s->natoms) * PP, 0.0);
-  std::vector<double> rnorm(p.nchannels);
-  for (int c = 0; c < p.nchannels; ++c) rnorm[c] = radial_norm(p.channels[c].l, p.channels[c].rc, rs);
-  int maxk = 0, maxrt = 0;
-  for (int a = 0; a < s->natoms; ++a) {
-    const double* R0 = p.positions + 3 * a;
-    int cnt = 0;
-    for (int ix = 0; ix < NX; ++ix)
-      for (int iy = 0; iy < NY; ++iy)
-        for (int iz = 0; iz < NZ; ++iz) {
-          double d[3] = {ix * h[0] - R0[0], iy * h[1] - R0[1], iz * h[2] - R0[2]};
-          for (int k = 0; k < 3; ++k) d[k] -= p.cell[k] * std::nearbyint(d[k] / p.cell[k]);
-          const double dist = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-          if (!(dist < rs)) continue;
-          double u[3] = {0, 0, 1};
-          if (dist > 0) {
-            u[0] = d[0] / dist;
-            u[1] = d[1] / dist;
-            u[2] = d[2] / dist;
-          }
-          pidx.push_back(iy * NZ + iz);
-          ix_of_row.push_back(ix);
-          for (int k = 0; k < 3; ++k) disp.push_back(R(d[k]));
-          std::vector<std::complex<double>> rowv(2 * PP, std::complex<double>(0, 0));
-          int pcount = 0;
-          for (int c = 0; c < p.nchannels; ++c) {
-            const nct_channel& ch = p.channels[c];
-            const double f = std::pow(dist, ch.l) * std::exp(-dist * dist / (2 * ch.rc * ch.rc)) / rnorm[c];
-            for (int twomj = -ch.twoj; twomj <= ch.twoj; twomj += 2) {
-              double cu, cd;
-              int mu, md;
-              spinor_coeffs(ch.l, ch.twoj, twomj, cu, mu, cd, md);
-              rowv[0 * PP + pcount] = f * cu * ylm(ch.l, mu, u[0], u[1], u[2]);
-              rowv[1 * PP + pcount] = f * cd * ylm(ch.l, md, u[0], u[1], u[2]);
-              energy[size_t(a) * PP + pcount] = ch.energy;
-              ++pcount;
-            }
-          }
-          beta.insert(beta.end(), rowv.begin(), rowv.end());
-          ++cnt;
-        }
-    row_off[a + 1] = row_off[a] + cnt;
-    maxk = std::max(maxk, (2 * cnt + 63) / 64);
-    maxrt = std::max(maxrt, (2 * cnt + 15) / 16);
-  }
-  const int Jtot = row_off[s->natoms];
-  // plane -> ranges
-  std::vector<int> pr_off(NX + 1, 0), pr_b, pr_e;
-  for (int x = 0; x < NX; ++x) {
-    for (int a = 0; a < s->natoms; ++a) {
-      int b = -1, e = -1;
-      for (int J = row_off[a]; J < row_off[a + 1]; ++J) {
-        if (ix_of_row[J] == x) {
-          if (b < 0) b = J;
-          e = J + 1;
-        }
-      }
-      if (b >= 0) {
-        pr_b.push_back(b);
-        pr_e.push_back(e);
-      }
-    }
-    pr_off[x + 1] = int(pr_b.size());
-  }
+  tables::ProjectorTables ht;
+  const std::string why = tables::build_projector_tables(s->n, p.cell, s->natoms, p.positions, p.nchannels,
+                                                         p.channels, p.r_sphere, ht);
+  if (!why.empty()) return fail(s, NCT_ERR_ARG, "projector tables: %s", why.c_str());
   ProjTables& pt = s->pt;
   pt.natoms = s->natoms;
-  pt.P = P;
-  pt.PP = PP;
-  pt.Jtot = Jtot;
-  pt.max_kchunks = std::max(maxk, 1);
-  pt.max_rowtiles = std::max(maxrt, 1);
+  pt.P = ht.P;
+  pt.PP = ht.PP;
+  pt.Jtot = ht.Jtot;
+  pt.max_kchunks = ht.max_kchunks;
+  pt.max_rowtiles = ht.max_rowtiles;
   int *d_row_off, *d_pidx, *d_pr_off, *d_pr_b, *d_pr_e;
   nct_status r;
-  if ((r = upload(s, row_off, &d_row_off)) != NCT_OK) return r;
-  if ((r = upload(s, pidx, &d_pidx)) != NCT_OK) return r;
-  if ((r = upload(s, pr_off, &d_pr_off)) != NCT_OK) return r;
-  if ((r = upload(s, pr_b, &d_pr_b)) != NCT_OK) return r;
-  if ((r = upload(s, pr_e, &d_pr_e)) != NCT_OK) return r;
-  if ((r = upload(s, energy, &s->energy_dev)) != NCT_OK) return r;
-  std::vector<R> braw(beta.size() * 2);
-  for (size_t k = 0; k < beta.size(); ++k) {
-    braw[2 * k] = R(beta[k].real());
-    braw[2 * k + 1] = R(beta[k].imag());
+  if ((r = upload(s, ht.row_off, &d_row_off)) != NCT_OK) return r;
+  if ((r = upload(s, ht.pidx, &d_pidx)) != NCT_OK) return r;
+  if ((r = upload(s, ht.pr_off, &d_pr_off)) != NCT_OK) return r;
+  if ((r = upload(s, ht.pr_begin, &d_pr_b)) != NCT_OK) return r;
+  if ((r = upload(s, ht.pr_end, &d_pr_e)) != NCT_OK) return r;
+  if ((r = upload(s, ht.energy, &s->energy_dev)) != NCT_OK) return r;
+  std::vector<R> braw(ht.beta.size() * 2);
+  for (size_t k = 0; k < ht.beta.size(); ++k) {
+    braw[2 * k] = R(ht.beta[k].real());
+    braw[2 * k + 1] = R(ht.beta[k].imag());
   }
   R* d_beta;
   if ((r = upload(s, braw, &d_beta)) != NCT_OK) return r;
+  std::vector<R> disp(ht.disp.begin(), ht.disp.end());
   R* d_disp;
   if ((r = upload(s, disp, &d_disp)) != NCT_OK) return r;
   pt.disp = d_disp;
@@ -514,13 +358,13 @@ nct_status build_projectors(nct_system* s) {
   pt.pr_end = d_pr_e;
   pt.beta = d_beta;
   pt.energy = s->energy_dev;
-  const size_t rows = size_t(s->S) * 2 * Jtot * s->cbytes;
+  const size_t rows = size_t(s->S) * 2 * pt.Jtot * s->cbytes;
   if ((r = dalloc(s, rows, &s->Wpsi)) != NCT_OK) return r;
   if ((r = dalloc(s, rows, &s->Wphi)) != NCT_OK) return r;
   if ((r = dalloc(s, rows, &s->Wwork)) != NCT_OK) return r;
   if ((r = dalloc(s, rows, &s->Y)) != NCT_OK) return r;
   if ((r = dalloc(s, rows, &s->Yphi)) != NCT_OK) return r;
-  const size_t cp = size_t(s->natoms) * PP * s->S;
+  const size_t cp = size_t(s->natoms) * pt.PP * s->S;
   if ((r = dalloc(s, cp * pt.max_kchunks * 16, &s->Cpart)) != NCT_OK) return r;
   if ((r = dalloc(s, cp * 16, &s->C)) != NCT_OK) return r;
   if ((r = dalloc(s, cp * s->cbytes, &s->EC)) != NCT_OK) return r;
