@@ -132,9 +132,12 @@ typedef struct {
   void *stream;               /* hipStream_t or NULL */
 } nct_params;
 
-/* Build a system: copies the parameters, builds FFT tables and the projector
- * tables of every atom, and allocates all device workspace.  External
- * potential starts at zero, B_ext at zero, fields self-consistent. */
+/* Build a system (the problem of Eq. TDSDFT for two-component spinor states, Sec. 3.1): copies
+ * the parameters, builds FFT tables and the projector tables of every atom (Eqs. Vps, Vps-soc),
+ * and allocates all device workspace.  External potential starts at zero, B_ext at zero, fields
+ * self-consistent.
+ * Errors: NCT_ERR_ARG (a parameter out of range; *out untouched), NCT_ERR_UNSUPPORTED (a grid
+ * size or plane pair not built, more than 32 projectors per atom), NCT_ERR_OOM, NCT_ERR_HIP. */
 nct_status nct_create_system(const nct_params *params, nct_system **out);
 
 /* Free every resource of the system (synchronises its stream). NULL is a no-op. */
@@ -188,9 +191,10 @@ nct_status nct_dm_initialization(nct_system *sys, const nct_atom_density *atoms,
 /* Ground state by self-consistent imaginary-time propagation (the paper does not specify its
  * solver): psi is first orthonormalised, then every iteration forms T_K(-tau H[rho]) psi (the
  * Taylor polynomial of exp(-tau H) of order params.taylor_order, through the same kernels as
- * the real-time step), orthonormalises it (Cholesky of the state overlap; the overlap and the
- * triangular transform are complex GEMMs of rocBLAS, the S x S factorisation runs on the host;
- * with k-points, within each run of consecutive states that share one Bloch vector)
+ * the real-time step), orthonormalises it (Cholesky of the state overlap: the overlap
+ * dV Psi^H Psi and the triangular change of basis Psi L^-H run on the matrix cores with FP64
+ * accumulation in either precision, the S x S factorisation on the host; with k-points, within
+ * each run of consecutive states that share one Bloch vector)
  * and recomputes rho and the fields from it.  keep_fields nonzero: the first iteration uses the
  * system's current fields (e.g. from nct_dm_initialization); 0: those of psi's own density.
  * With frozen fields they stay frozen.  energies_host, if non-NULL, receives [niter] total
@@ -223,7 +227,8 @@ nct_status nct_set_laser_gauge(nct_system *sys, int gauge);
  * Errors: NCT_ERR_ARG for a non-finite component. */
 nct_status nct_set_kpoints(nct_system *sys, const double *kvec);
 
-/* Set the potentials of Eq. (HNC-SDFT):
+/* Set the potentials of Eq. (HNC-SDFT) and the external field of the Zeeman term
+ * (Eq. zeeman_potential):
  *   v_ext_dev  device double [N]: external local potential v_ext(r) (copied), or NULL to keep;
  *   b          host: B_ext(t) description (copied), or NULL to keep;
  *   fields_dev device double [4][N] {v, b_x, b_y, b_z}: if non-NULL, the total local fields
@@ -233,7 +238,9 @@ nct_status nct_set_kpoints(nct_system *sys, const double *kvec);
 nct_status nct_set_potentials(nct_system *sys, const double *v_ext_dev, const nct_bfield *b,
                               const double *fields_dev);
 
-/* Spin density of psi (Eq. density4):
+/* Spin density of psi (Eq. density4; n and m from it by Eqs. rho1-3), and optionally the fields
+ * of Eq. (HNC-SDFT) that follow from it (Hartree, Eq. KSpot; exchange-correlation, Eqs. LC+ALDA2,
+ * LC+ALDA):
  *   rho_v_dev    device double [4][N] {rho_uu, rho_dd, Re rho_ud, Im rho_ud}, or NULL;
  *   totals_host  host double[4] {N_e, M_x, M_y, M_z} (integrated), or NULL (synchronises);
  *   update_fields  nonzero: recompute v_H and the exchange fields from this density and keep
@@ -246,12 +253,17 @@ nct_status nct_density_magnetization(nct_system *sys, const void *psi_dev, doubl
  * (v = v_ext + v_E(t) + v_H + vbar_xc, b = b_xc + mu_B B_ext(t); v_E is zero without a laser). */
 nct_status nct_get_fields(nct_system *sys, double t, double *fields_dev);
 
-/* hpsi = H psi with the current fields, B_ext(t) and v_E(t) (psi and hpsi distinct buffers of
- * the psi layout above). */
+/* hpsi = H psi: the spinor Kohn-Sham Hamiltonian of Eqs. (TDSDFT) and (HNC-SDFT) with the
+ * pseudopotential of Eqs. (Vps), (Vps-soc): -1/2 nabla^2 + [v + b.sigma] + V_NL, with the current
+ * fields, B_ext(t) and v_E(t).  psi and hpsi are distinct device buffers of the psi layout above
+ * (caller-owned; hpsi is overwritten).
+ * Errors: NCT_ERR_ARG (NULL or identical buffers), NCT_ERR_STATE (no fields yet: call
+ * nct_density_magnetization with update_fields, or freeze fields with nct_set_potentials). */
 nct_status nct_apply_hamiltonian(nct_system *sys, const void *psi_dev, void *hpsi_dev, double t);
 
-/* Advance psi in place by nsteps ETRS steps from time t0.  The fields of the first step are
- * computed from psi itself.  obs_host, if non-NULL, receives [nsteps][13] doubles after each
+/* Advance psi in place by nsteps steps of Eq. (TDSDFT) from time t0, each one enforced
+ * time-reversal-symmetry step (the paper names no propagator; see the top of this file).  The
+ * fields of the first step are computed from psi itself.  obs_host, if non-NULL, receives [nsteps][13] doubles after each
  * step: t, N_e, M_x, M_y, M_z, E_total, E_kin, E_loc, E_NL, E_H, E_xc, E_Z,
  * max_i |<psi_i|psi_i> - 1|, with
  *   E = sum_i f_i <psi_i|T|psi_i> + int (v_ext + v_E(t)) n + sum_i f_i sum_p E_p |C_p,i|^2
@@ -276,7 +288,10 @@ nct_status nct_set_watchdog(nct_system *sys, double max_rel_drift);
 nct_status nct_magnetization_seed(nct_system *sys, const void *psi_dev, const double *w,
                                   void *lam_dev);
 
-/* Reverse-mode (adjoint) of one ETRS step n -> n+1.  With lam = 2 dL/dpsi* (so that
+/* Reverse-mode (adjoint) of one step of nct_step, n -> n+1: the transpose of the step's
+ * linearisation (the paper has no adjoint; this is the derivative of the discrete step of
+ * Eq. TDSDFT as nct_step computes it, used for gradients of M(T) with respect to the pulse
+ * parameters of B_ext).  With lam = 2 dL/dpsi* (so that
  * dL = Re sum lam^* dpsi), given lam_{n+1} returns lam_n, including the response of the
  * Hartree and exchange(-correlation) fields to the density at psi_n and psi~.  The forward quantities come
  * from tape record tape_index of the last taped nct_step, or, when tape_index < 0, are

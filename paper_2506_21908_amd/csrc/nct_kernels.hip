@@ -472,6 +472,209 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ), plane2_min_waves<R>(NY* 
   }
 }
 
+// ---------------------------------------------------------------- plane pass, one plane in LDS
+// Same stage as k_plane_stage2 for planes where two LDS planes would admit only one workgroup per
+// CU but one plane admits two (FP64 64^2: 67 KB; FP32 96^2: 76 KB).  The spinor components go
+// through the single LDS plane one after the other: the up component's kinetic part waits in
+// registers (PPT values per thread) while the down component is transformed; after the 2x2 update
+// the up result waits there again while the down result is finished and transformed forward.
+// Two resident workgroups per CU interleave their memory and transform phases.
+// Threads per workgroup (tuning macro) and the point batch of the 2x2 update.
+#ifndef NCT_PLANER_NT
+#define NCT_PLANER_NT 512
+#endif
+// NCT_PLANER_OFF (tuning macro) keeps those planes on the two-plane kernel.
+template <typename R, int NY, int NZ>
+constexpr bool planer_use() {
+#ifdef NCT_PLANER_OFF
+  return false;
+#else
+  return plane2_lds_bytes<NY, NZ>(sizeof(cpx<R>)) > 80 * 1024 &&
+         plane_lds_bytes<NY, NZ>(sizeof(cpx<R>)) <= 80 * 1024 - 512;
+#endif
+}
+
+template <typename R, int NY, int NZ, int M>
+__global__ __launch_bounds__(NCT_PLANER_NT, 4) void k_plane_stage_r(StageArgs<R> a, ProjTables pt,
+                                                                     const cpx<R>* __restrict__ twy_g,
+                                                                     const cpx<R>* __restrict__ twz_g,
+                                                                     int S, int NX) {
+  constexpr int NP = NY * NZ;
+  constexpr int NT = NCT_PLANER_NT;
+  constexpr int PZ = NZ + 1;
+  constexpr int PPT = (NP + NT - 1) / NT;
+  constexpr int G = sizeof(R) == 8 ? 2 : 3;  // points per load batch of the 2x2 update
+  extern __shared__ double4 smem_d4[];
+  cpx<R>* pl = reinterpret_cast<cpx<R>*>(smem_d4);
+  cpx<R>* twy = pl + NY * PZ;
+  cpx<R>* twz = twy + NY;
+  const int tid = threadIdx.x;
+  const int L = xcd_logical(blockIdx.x, gridDim.x);
+  const int x = L / S;
+  const int i = L - x * S;
+  for (int k = tid; k < NY; k += NT) twy[k] = twy_g[k];
+  for (int k = tid; k < NZ; k += NT) twz[k] = twz_g[k];
+  const size_t N = size_t(NX) * NP;
+  const size_t off0 = (size_t(2 * i) * NX + x) * NP;
+  const size_t off1 = (size_t(2 * i + 1) * NX + x) * NP;
+  const cpx<R>* __restrict__ tin = reinterpret_cast<const cpx<R>*>(a.tmp_in);
+
+  // 1) kinetic part of the up component (inverse 2D transform), kept in registers
+  plane_fft_inv_from<R, NY, NZ, PZ, NT>(pl, twy, twz, tid, [&](int g) { return ld_stream<M>(&tin[off0 + g]); });
+  cpx<R> ku[PPT];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int e = min(tid + j * NT, NP - 1);
+    ku[j] = pl[(e / NZ) * PZ + (e % NZ)];
+  }
+  __syncthreads();
+  // 2) kinetic part of the down component, left in LDS
+  plane_fft_inv_from<R, NY, NZ, PZ, NT>(pl, twy, twz, tid, [&](int g) { return ld_stream<M>(&tin[off1 + g]); });
+
+  // 3) 2x2 local potential and Taylor update: up result back into ku, down result into LDS
+  {
+    const cpx<R>* __restrict__ win = reinterpret_cast<const cpx<R>*>(a.w_in);
+    const cpx<R>* __restrict__ xb = reinterpret_cast<const cpx<R>*>(a.x_base);
+    const bool xsep = xb && (a.x_base != a.w_in);
+    const R* __restrict__ F = a.fields;
+    const R lx = a.lg[0] * R(x) + a.lg[3];  // laser potential of this plane, less its y, z terms
+#pragma unroll
+    for (int j0 = 0; j0 < PPT; j0 += G) {
+      cpx<R> wu[G], wd[G], xu[G], xd[G];
+      R fv[G], fx[G], fy[G], fz[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if (j0 + g < PPT) {
+          const int e = min(tid + (j0 + g) * NT, NP - 1);  // clamped: loads unconditional
+          const size_t p = size_t(x) * NP + e;
+          wu[g] = ld_stream<M>(&win[off0 + e]);
+          wd[g] = ld_stream<M>(&win[off1 + e]);
+          if (xsep) {
+            xu[g] = ld_stream<M>(&xb[off0 + e]);
+            xd[g] = ld_stream<M>(&xb[off1 + e]);
+          } else {
+            xu[g] = wu[g];
+            xd[g] = wd[g];
+          }
+          fv[g] = F[p];
+          fx[g] = F[N + p];
+          fy[g] = F[2 * N + p];
+          fz[g] = F[3 * N + p];
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int j = j0 + g;
+        const int e = tid + j * NT;
+        if (j < PPT && e < NP) {
+          const int q = (e / NZ) * PZ + (e % NZ);
+          const cpx<R> tu = ku[j], td = pl[q];
+          const R v = fv[g] + (lx + a.lg[1] * R(e / NZ) + a.lg[2] * R(e % NZ));
+          const R bx = fx[g] + a.bext[0], by = fy[g] + a.bext[1], bz = fz[g] + a.bext[2];
+          cpx<R> hu, hd;
+          hu.x = tu.x + (v + bz) * wu[g].x + bx * wd[g].x + by * wd[g].y;
+          hu.y = tu.y + (v + bz) * wu[g].y + bx * wd[g].y - by * wd[g].x;
+          hd.x = td.x + bx * wu[g].x - by * wu[g].y + (v - bz) * wd[g].x;
+          hd.y = td.y + bx * wu[g].y + by * wu[g].x + (v - bz) * wd[g].y;
+          cpx<R> ou = {a.cre * hu.x - a.cim * hu.y, a.cre * hu.y + a.cim * hu.x};
+          cpx<R> od = {a.cre * hd.x - a.cim * hd.y, a.cre * hd.y + a.cim * hd.x};
+          if (xb) {
+            ou.x += a.alpha * xu[g].x;
+            ou.y += a.alpha * xu[g].y;
+            od.x += a.alpha * xd[g].x;
+            od.y += a.alpha * xd[g].y;
+          }
+          ku[j] = ou;
+          pl[q] = od;
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // 4) per component (down, then up): projector rows, outputs, forward transform
+  const cpx<R>* __restrict__ Y = reinterpret_cast<const cpx<R>*>(a.Y);
+  cpx<R>* __restrict__ Wr = reinterpret_cast<cpx<R>*>(a.W);
+  cpx<R>* __restrict__ wout = reinterpret_cast<cpx<R>*>(a.w_out);
+  cpx<R>* __restrict__ acc = reinterpret_cast<cpx<R>*>(a.acc);
+  cpx<R>* __restrict__ tout = reinterpret_cast<cpx<R>*>(a.tmp_out);
+  const int r0 = pt.pr_off ? pt.pr_off[x] : 0;
+  const int r1 = pt.pr_off ? pt.pr_off[x + 1] : 0;
+  const bool kq = a.kv != nullptr;
+  R q0 = 0, q1 = 0, q2 = 0;
+  if (kq) {
+    const R* k0 = a.kv + 3 * (a.state_off + i);
+    q0 = k0[0] + a.ka[0];
+    q1 = k0[1] + a.ka[1];
+    q2 = k0[2] + a.ka[2];
+  }
+  const R* disp = reinterpret_cast<const R*>(pt.disp);
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    const int h = 1 - pass;  // spinor component finished in this pass
+    const size_t offh = h ? off1 : off0;
+    if (pass == 1) {
+      // the down component's forward transform has read LDS for the last time: reuse it for up
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const int e = tid + j * NT;
+        if (e < NP) pl[(e / NZ) * PZ + (e % NZ)] = ku[j];
+      }
+      __syncthreads();
+    }
+    const size_t rowbase = size_t(2 * i + h) * pt.Jtot;
+    if (Y) {
+      for (int r = r0; r < r1; ++r) {
+        const int jb = pt.pr_begin[r], je = pt.pr_end[r];
+        for (int J = jb + tid; J < je; J += NT) {
+          const int e = pt.pidx[J];
+          cpx<R> y = Y[rowbase + J];
+          if (kq) y = cmulc(y, bloch_phase(q0, q1, q2, disp + 3 * J));
+          cpx<R>& d = pl[(e / NZ) * PZ + (e % NZ)];
+          d.x += a.cre * y.x - a.cim * y.y;
+          d.y += a.cre * y.y + a.cim * y.x;
+        }
+        __syncthreads();
+      }
+    }
+    if (Wr) {
+      for (int r = r0; r < r1; ++r) {
+        const int jb = pt.pr_begin[r], je = pt.pr_end[r];
+        for (int J = jb + tid; J < je; J += NT) {
+          const int e = pt.pidx[J];
+          cpx<R> o = pl[(e / NZ) * PZ + (e % NZ)];
+          if (kq) o = cmul(o, bloch_phase(q0, q1, q2, disp + 3 * J));
+          Wr[rowbase + J] = o;
+        }
+      }
+    }
+    if (acc) {
+      cpx<R> v[PPT];
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) v[j] = acc[offh + min(tid + j * NT, NP - 1)];
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const int e = tid + j * NT;
+        if (e < NP) acc[offh + e] = v[j] + pl[(e / NZ) * PZ + (e % NZ)];
+      }
+    }
+    if (wout) {
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const int e = tid + j * NT;
+        if (e < NP) st_stream<M>(&wout[offh + e], pl[(e / NZ) * PZ + (e % NZ)]);
+      }
+    }
+    if (tout) {
+      __syncthreads();
+      cpx<R>* __restrict__ to = tout + offh;
+      plane_fft_fwd_to<R, NY, NZ, PZ, NT>(pl, twy, twz, tid, [](int) { return 0; },
+                                          [&](int g, int, cpx<R> v, int) { st_stream<M>(&to[g], v); });
+    }
+  }
+}
+
 // ---------------------------------------------------------------- plane pass: transform only
 // SRC: what `in` holds: 0 complex values; 1 a spin density rho_v (real, [4][N]; the transform
 // takes n = rho_uu + rho_dd), 2 a real array (the transform takes it as the real part).
@@ -1596,7 +1799,13 @@ static hipError_t launch_plane_stage_m(int S, int NX, const StageArgs<R>& a, con
   const unsigned grid = unsigned(S) * unsigned(NX);
   const auto ty = reinterpret_cast<const cpx<R>*>(twy);
   const auto tz = reinterpret_cast<const cpx<R>*>(twz);
-  if constexpr (plane2_fits<R, A, B>()) {
+  if constexpr (planer_use<R, A, B>()) {
+    constexpr size_t ldsr = plane_lds_bytes<A, B>(sizeof(cpx<R>));
+    auto kernr = k_plane_stage_r<R, A, B, M>;
+    hipError_t er = set_lds(kernr, ldsr);
+    if (er != hipSuccess) return er;
+    nct_launch(kernr, dim3(grid), dim3(NCT_PLANER_NT), ldsr, st, a, pt, ty, tz, S, NX);
+  } else if constexpr (plane2_fits<R, A, B>()) {
     constexpr size_t lds2 = plane2_lds_bytes<A, B>(sizeof(cpx<R>));
     auto kern2 = k_plane_stage2<R, A, B, M>;
     hipError_t e2 = set_lds(kern2, lds2);

@@ -1,0 +1,110 @@
+"""Self-consistent steps and adjoint steps on the full 64^3 and 96^3 grids against the oracle.
+
+The benchmark-shaped workloads at these grids carry 256 and 512 states, more than the oracle can
+step in a test; here the grids, cells (h = 0.42 bohr) and plane-pass instantiations are theirs,
+with a few states: 2 atoms x 18 KB+SOC projectors, Gaussian local potential, Slater exchange +
+Hartree and a circular B pulse.  The FP64 path must match the oracle to 1e-10 point by point
+(psi, n, m) and in every observable, the FP32-mixed form to 1e-5; the adjoint step must satisfy
+Re<lam_n, dpsi> = Re<lam_{n+1}, J dpsi> with J the oracle's tangent-linear step (1e-10 in FP64,
+1e-5 in FP32-mixed) and give the oracle's dL/dB.
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import nct_oracle as O
+from paper_2506_21908_amd import inputs as I
+from parity_metrics import max_rel, nm_errors, traj_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _system(n, S, case, xc=1):
+    L = 0.42 * n
+    bf = I.BField(B0=(0.0, 0.0, 0.01), pulses=I.circular_pulses([0.05], [0.5], 0.05, 0.1))
+    return I.make_system(n=(n, n, n), L=(L, L, L), nstates=S, natoms=2, case=case, bfield=bf,
+                         full_spinors=False, min_sep=5.0, xc=xc)
+
+
+@pytest.mark.parametrize("n,prec", [(64, "fp64"), (64, "mixed"), (96, "fp64"), (96, "mixed")])
+def test_full_grid_scf_steps_vs_oracle(torch_cuda, n, prec):
+    from paper_2506_21908_amd import nct
+    w = _system(n, 4, 70 + n)
+    nsteps = 2
+    say(f"{n}^3 x 4 spinors, 2 atoms, {prec}: {nsteps} self-consistent steps vs oracle")
+    sysd = O.system_from_workload(w)
+    t0 = time.time()
+    psi_ref, obs_ref = O.run(sysd, w.psi0, nsteps)
+    say(f"  oracle {time.time() - t0:.1f} s")
+    pf = nct.NCT_FP64 if prec == "fp64" else nct.NCT_FP32_MIXED
+    s = nct.system_from_workload(w, precision=pf)
+    psi = nct.states_to_device(w.psi0, pf)
+    obs = s.step(psi, 0.0, nsteps, obs=True)
+    got = psi.cpu().numpy().astype(np.complex128)
+    e_N, e_M, e_E = traj_errors(obs, obs_ref[1:])
+    e_n, e_m, _, _ = nm_errors(got, psi_ref, sysd.occ)
+    e_psi = max_rel(got, psi_ref)
+    say(f"  N_e {e_N:.2e} M {e_M:.2e} E {e_E:.2e} n {e_n:.2e} m {e_m:.2e} psi {e_psi:.2e} (max-abs)")
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    assert max(e_N, e_M, e_E, e_n, e_m, e_psi) < tol
+
+
+def _rand_states(shape, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("n,prec", [(64, "fp64"), (96, "mixed")])
+def test_full_grid_backward_step_vs_oracle_tangent_linear(torch_cuda, n, prec):
+    """Dot-product identity of the adjoint step (recompute mode) with the oracle's tangent-linear
+    step, and dL/dB(t_n), dL/dB(t_n + dt) against the oracle's response to dB (1e-4 in FP32-mixed:
+    each is a sum over the grid of FP32 products)."""
+    torch = torch_cuda
+    from paper_2506_21908_amd import nct
+    w = _system(n, 2, 80 + n)
+    say(f"{n}^3 x 2 spinors {prec}: backward step vs oracle tangent-linear step")
+    sysd = O.system_from_workload(w)
+    t_n = 0.05
+    lam1 = _rand_states(w.psi0.shape, 1)
+    dpsi = _rand_states(w.psi0.shape, 2)
+    pf = nct.NCT_FP64 if prec == "fp64" else nct.NCT_FP32_MIXED
+    tol = 1e-10 if prec == "fp64" else 1e-5
+    if prec != "fp64":   # the oracle sees the FP32-rounded inputs of the FP32 path
+        w.psi0 = w.psi0.astype(np.complex64).astype(np.complex128)
+        lam1 = lam1.astype(np.complex64).astype(np.complex128)
+    t0 = time.time()
+    _, dnext = O.etrs_step_jvp(sysd, w.psi0, dpsi, t_n, np.zeros(3), np.zeros(3))
+    say(f"  oracle tangent-linear step {time.time() - t0:.1f} s")
+    s = nct.system_from_workload(w, precision=pf)
+    psi = nct.states_to_device(w.psi0, pf)
+    lam_in = nct.states_to_device(lam1, pf)
+    lam_out = torch.empty_like(lam_in)
+    dLdB = s.backward_step(-1, psi, t_n, lam_in, lam_out)
+    lhs = float(np.real(np.vdot(lam_out.cpu().numpy().astype(np.complex128), dpsi)))
+    rhs = float(np.real(np.vdot(lam1, dnext)))
+    say(f"  <lam_n, dpsi> = {lhs:.15e}  <lam_n+1, J dpsi> = {rhs:.15e}  rel {abs(lhs - rhs) / abs(rhs):.2e}")
+    assert abs(lhs - rhs) < tol * abs(rhs)
+    for j in (2, 3):   # dL/dB_z(t_n) and dL/dB_x(t_n + dt)
+        e = np.zeros(3)
+        e[j % 3] = 1.0
+        dBn, dBp = (e, np.zeros(3)) if j < 3 else (np.zeros(3), e)
+        _, dn2 = O.etrs_step_jvp(sysd, w.psi0, np.zeros_like(dpsi), t_n, dBn, dBp)
+        ref = float(np.real(np.vdot(lam1, dn2)))
+        say(f"  dL/dB[{j}] gpu {dLdB[j]:.12e} oracle {ref:.12e}")
+        tol_b = 1e-10 if prec == "fp64" else 1e-4   # a field sum over the grid of FP32 products
+        assert abs(dLdB[j] - ref) < tol_b * max(abs(ref), 1e-3 * np.max(np.abs(dLdB)))
