@@ -249,6 +249,22 @@ nct_status nct_set_potentials(nct_system *sys, const double *v_ext_dev, const nc
 nct_status nct_density_magnetization(nct_system *sys, const void *psi_dev, double t,
                                      double *rho_v_dev, double *totals_host, int update_fields);
 
+/* Allocation-free variant of nct_density_magnetization, for callers that cannot allocate device
+ * memory during the call (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and synchronisation as nct_density_magnetization; it calls
+ * no hipMalloc, hipFree or allocating library routine.  The temporaries of its kernels (Poisson
+ * work, the fields output when update_fields is 0, block partial sums and totals) live in a static
+ * device array of NCT_STATIC_SCRATCH_BYTES (32 MiB) that the library holds on every device it runs
+ * on until the process ends: it takes 48 N bytes plus a little, which admits grids up to about
+ * 690,000 points (64 x 96 x 96, not 96^3).  That array is shared by every system on the device and keeps the last
+ * call's contents: calls that overlap on one device (two host threads, or work on two streams not
+ * ordered by events) race.
+ * Errors: as nct_density_magnetization, plus NCT_ERR_UNSUPPORTED (before any work) when the grid
+ * needs more than the array holds, and NCT_ERR_HIP if the array's address could not be looked up
+ * when the system was created. */
+nct_status nct_density_magnetization_static(nct_system *sys, const void *psi_dev, double t,
+                                            double *rho_v_dev, double *totals_host, int update_fields);
+
 /* Current total local fields at time t into device double [4][N] {v, b_x, b_y, b_z}
  * (v = v_ext + v_E(t) + v_H + vbar_xc, b = b_xc + mu_B B_ext(t); v_E is zero without a laser). */
 nct_status nct_get_fields(nct_system *sys, double t, double *fields_dev);

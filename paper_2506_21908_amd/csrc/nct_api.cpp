@@ -65,6 +65,10 @@ struct nct_system {
   void* ECB = nullptr;
   std::string err;
   std::vector<DevBuf> owned;
+  // the static scratch array of this system's device (allocation-free entry point), or null
+  void* scr = nullptr;
+  size_t scr_bytes = 0;
+  std::string scr_err;
 
   // host copies
   std::vector<double> occ_h;
@@ -518,34 +522,45 @@ struct Engine {
 
   // where the next field update also records its electron count (per-step watchdog), or null
   double* ne_slot = nullptr;
+  // temporaries of the field update: the system's own buffers unless set (the allocation-free
+  // entry point points them into the static scratch array)
+  void* w_ncpx = nullptr;     // complex double [N] Poisson work
+  double* w_fscr = nullptr;   // [4][N] fields output when they are not kept
+  double* w_fpart = nullptr;  // [nblk][kFieldTot] block partial sums
+  double* w_ftot = nullptr;   // [kFieldTot] totals
+  void* ncpx() const { return w_ncpx ? w_ncpx : s->ncpx; }
+  double* fscr() const { return w_fscr ? w_fscr : s->fields_scr; }
+  double* fpart() const { return w_fpart ? w_fpart : s->fpart; }
+  double* ftot() const { return w_ftot ? w_ftot : s->ftot; }
 
   // Hartree + exchange fields from the density in s->rho (FP64 throughout)
   nct_status fields_from_rho(bool store) {
     nct_status r;
+    void* const pw = ncpx();
     const double* vh = nullptr;
     const double N = double(s->N);
     const int K = NCT_K_FIELDS;
     if (s->prm.hartree) {
       if ((r = check(timed(s, K, 32 * N, 0, [&] {
-             return launch_plane_fwd_real(s->n, s->rho, 1, s->ncpx, s->tw64[1], s->tw64[2], s->st); }),
+             return launch_plane_fwd_real(s->n, s->rho, 1, pw, s->tw64[1], s->tw64[2], s->st); }),
                      "poisson fwd")) != NCT_OK) return r;
       if ((r = check(timed(s, K, 32 * N, 0, [&] {
-             return launch_xpass<double>(s->n, 1, s->ncpx, s->ncpx, s->g2x64, s->g2yz64,
+             return launch_xpass<double>(s->n, 1, pw, pw, s->g2x64, s->g2yz64,
                                          4.0 * kPi / double(s->N), 1, s->tw64[0], s->st); }),
                      "poisson x")) != NCT_OK) return r;
       if ((r = check(timed(s, K, 32 * N, 0, [&] {
-             return launch_plane_inv<double>(s->n, 1, s->ncpx, s->ncpx, 1.0, s->tw64[1], s->tw64[2],
+             return launch_plane_inv<double>(s->n, 1, pw, pw, 1.0, s->tw64[1], s->tw64[2],
                                              s->st); }), "poisson inv")) != NCT_OK) return r;
-      vh = reinterpret_cast<const double*>(s->ncpx);  // v_H: the real parts
+      vh = reinterpret_cast<const double*>(pw);  // v_H: the real parts
     }
     int nb = 0;
-    double* out = store ? s->fields : s->fields_scr;
+    double* out = store ? s->fields : fscr();
     float* o32 = (store && !s->fp64) ? s->fields32 : nullptr;
     if ((r = check(timed(s, K, (32 + 16 + 32 + (o32 ? 16 : 0)) * N, 0, [&] {
            return launch_fields(s->rho, s->vext, vh, s->prm.xc, s->prm.m_threshold, s->n, s->prm.cell, out, o32,
-                                s->fpart, &nb, s->st); }), "fields")) != NCT_OK) return r;
+                                fpart(), &nb, s->st); }), "fields")) != NCT_OK) return r;
     if ((r = check(timed(s, K, 8.0 * kFieldTot * nb, 0, [&] {
-           return launch_reduce_rows(s->fpart, nb, kFieldTot, s->ftot, s->st, ne_slot); }),
+           return launch_reduce_rows(fpart(), nb, kFieldTot, ftot(), s->st, ne_slot); }),
                    "reduce")) != NCT_OK) return r;
     if (store) s->fields_valid = true;
     return NCT_OK;
@@ -1509,6 +1524,18 @@ nct_status create_impl(const nct_params* p, nct_system** out) {
       if ((r = dalloc(s, cp * s->cbytes, &s->ECB)) != NCT_OK) return bail(r);
     }
   }
+  {  // this device's static scratch (allocation-free entry point): looked up once per device
+    void* sp = nullptr;
+    size_t sb = 0;
+    const hipError_t es = static_scratch(&sp, &sb);
+    if (es == hipSuccess) {
+      s->scr = sp;
+      s->scr_bytes = sb;
+    } else {
+      (void)hipGetLastError();
+      s->scr_err = hipGetErrorString(es);
+    }
+  }
   hipError_t e = hipMemsetAsync(s->vext, 0, N * 8, s->st);
   if (e == hipSuccess) e = hipMemsetAsync(s->fields, 0, 4 * N * 8, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
@@ -1521,6 +1548,50 @@ nct_status create_impl(const nct_params* p, nct_system** out) {
 }
 
 }  // namespace
+
+// Same work as nct_density_magnetization; the temporaries of its kernels (Poisson work, the
+// fields output when they are not kept, block partial sums and totals) are slices of this
+// device's static scratch array, so the call allocates nothing.
+template <typename R>
+static nct_status density_magnetization_static(nct_system* s, const void* psi, double* rho_v_dev,
+                                               double* totals_host, int update_fields) {
+  const size_t N = s->N;
+  const size_t nblk = (N + 255) / 256;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 255) / 256 * 256;
+    return o;
+  };
+  const size_t o_ncpx = take(N * 16);
+  const size_t o_fscr = take(4 * N * 8);
+  const size_t o_fpart = take(nblk * kFieldTot * 8);
+  const size_t o_ftot = take(kFieldTot * 8);
+  if (!s->scr) return fail(s, NCT_ERR_HIP, "static scratch unavailable: %s", s->scr_err.c_str());
+  if (off > s->scr_bytes)
+    return fail(s, NCT_ERR_UNSUPPORTED, "this grid needs %zu bytes of static scratch; the library holds %zu",
+                off, s->scr_bytes);
+  char* base = static_cast<char*>(s->scr);
+  Engine<R> E{s};
+  E.w_ncpx = base + o_ncpx;
+  E.w_fscr = reinterpret_cast<double*>(base + o_fscr);
+  E.w_fpart = reinterpret_cast<double*>(base + o_fpart);
+  E.w_ftot = reinterpret_cast<double*>(base + o_ftot);
+  nct_status r = E.density(psi);
+  if (r != NCT_OK) return r;
+  if (update_fields || totals_host) {
+    if ((r = E.fields_from_rho(update_fields != 0)) != NCT_OK) return r;
+  }
+  if (rho_v_dev) HIPCHK(s, hipMemcpyAsync(rho_v_dev, s->rho, 4 * N * 8, hipMemcpyDeviceToDevice, s->st));
+  if (totals_host) {
+    double tot[4];
+    HIPCHK(s, hipMemcpyAsync(tot, E.w_ftot, sizeof(tot), hipMemcpyDeviceToHost, s->st));
+    HIPCHK(s, hipStreamSynchronize(s->st));
+    for (int k = 0; k < 4; ++k) totals_host[k] = tot[k] * s->dV;
+    if (!std::isfinite(tot[0])) return fail(s, NCT_ERR_NONFINITE, "non-finite density");
+  }
+  return NCT_OK;
+}
 
 // ================================================================ C ABI
 extern "C" {
@@ -1726,6 +1797,15 @@ nct_status nct_density_magnetization(nct_system* s, const void* psi, double t, d
     if (!std::isfinite(tot[0])) return fail(s, NCT_ERR_NONFINITE, "non-finite density");
   }
   return NCT_OK;
+}
+
+nct_status nct_density_magnetization_static(nct_system* s, const void* psi, double t, double* rho_v_dev,
+                                            double* totals_host, int update_fields) {
+  (void)t;
+  if (!s || !psi) return s ? fail(s, NCT_ERR_ARG, "psi is NULL") : NCT_ERR_ARG;
+  if (update_fields && s->frozen) return fail(s, NCT_ERR_STATE, "fields are frozen");
+  if (s->fp64) return density_magnetization_static<double>(s, psi, rho_v_dev, totals_host, update_fields);
+  return density_magnetization_static<float>(s, psi, rho_v_dev, totals_host, update_fields);
 }
 
 nct_status nct_get_fields(nct_system* s, double t, double* out) {

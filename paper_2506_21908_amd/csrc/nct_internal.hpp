@@ -201,6 +201,15 @@ hipError_t launch_gram(const void* A, int S, size_t K, double scale, void* part,
 template <typename R>
 hipError_t launch_basis_transform(const void* A, const void* Mt, int S, size_t K, void* D, hipStream_t st);
 
+// Static device scratch of the allocation-free entry point (nct_density_magnetization_static):
+// a file-scope array of NCT_STATIC_SCRATCH_BYTES on every device the library runs on, alive until
+// the process ends.  static_scratch() returns its device address on the current device (looked up
+// once per device, with that device current) and its size.
+#ifndef NCT_STATIC_SCRATCH_BYTES
+#define NCT_STATIC_SCRATCH_BYTES (size_t(32) << 20)
+#endif
+hipError_t static_scratch(void** ptr, size_t* bytes);
+
 bool plane_pair_supported(int ny, int nz);
 bool line_supported(int n);
 

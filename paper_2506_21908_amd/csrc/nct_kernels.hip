@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "nct_fft.hpp"
 #include "nct_internal.hpp"
@@ -1745,6 +1746,31 @@ __global__ __launch_bounds__(256) void k_basis_transform(const cpx<R>* __restric
       if (j < S && pp < K) D[size_t(j) * K + pp] = {R(dr[h][r]), R(di[h][r])};
     }
   }
+}
+
+// ---------------------------------------------------------------- static scratch
+// Temporaries of the allocation-free entry point.  Host code never passes this name to a kernel:
+// it takes the per-device address from static_scratch().
+static __device__ __align__(256) unsigned char scratch[NCT_STATIC_SCRATCH_BYTES];
+
+hipError_t static_scratch(void** ptr, size_t* bytes) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {  // once per device, with that device current
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  *bytes = NCT_STATIC_SCRATCH_BYTES;
+  return hipSuccess;
 }
 
 // ================================================================ launchers

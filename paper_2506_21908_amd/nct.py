@@ -95,6 +95,9 @@ def lib():
         L.nct_density_magnetization.argtypes = [c_void_p, c_void_p, c_double, c_void_p,
                                                 POINTER(c_double), c_int]
         L.nct_density_magnetization.restype = c_int
+        L.nct_density_magnetization_static.argtypes = [c_void_p, c_void_p, c_double, c_void_p,
+                                                       POINTER(c_double), c_int]
+        L.nct_density_magnetization_static.restype = c_int
         L.nct_get_fields.argtypes = [c_void_p, c_double, c_void_p]
         L.nct_get_fields.restype = c_int
         L.nct_apply_hamiltonian.argtypes = [c_void_p, c_void_p, c_void_p, c_double]
@@ -276,6 +279,16 @@ class System:
         self._check(lib().nct_density_magnetization(self.h, _tptr(psi), float(t), _tptr(rho_v),
                                                      _dptr(tot) if totals else None,
                                                      int(update_fields)))
+        return tot if totals else None
+
+    def density_magnetization_static(self, psi, t: float = 0.0, rho_v=None, totals: bool = False,
+                                     update_fields: bool = False):
+        """nct_density_magnetization_static: the same results with every temporary in the
+        library's static device array (no allocation during the call)."""
+        tot = np.zeros(4)
+        self._check(lib().nct_density_magnetization_static(self.h, _tptr(psi), float(t), _tptr(rho_v),
+                                                            _dptr(tot) if totals else None,
+                                                            int(update_fields)))
         return tot if totals else None
 
     def get_fields(self, t: float, out):
