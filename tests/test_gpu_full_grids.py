@@ -76,8 +76,12 @@ def test_full_grid_backward_step_vs_oracle_tangent_linear(torch_cuda, n, prec):
     each is a sum over the grid of FP32 products)."""
     torch = torch_cuda
     from paper_2506_21908_amd import nct
-    w = _system(n, 2, 80 + n)
-    say(f"{n}^3 x 2 spinors {prec}: backward step vs oracle tangent-linear step")
+    # four states: three spin along n and one along -n.  With two states both would point along
+    # n, every point would be fully polarised, and the minority density n - |m| would be zero up
+    # to rounding: Slater's n_-^(1/3) then amplifies rounding, and the tangent of the exchange
+    # field is ill-conditioned (the identity drifts to ~1e-5 on both sides of the comparison).
+    w = _system(n, 4, 80 + n)
+    say(f"{n}^3 x 4 spinors {prec}: backward step vs oracle tangent-linear step")
     sysd = O.system_from_workload(w)
     t_n = 0.05
     lam1 = _rand_states(w.psi0.shape, 1)
