@@ -17,6 +17,10 @@ HBM.  One JSON line follows, with
   fp32_mixed    the same workload in the FP32-mixed form, with its own roofline
   large         the 96^3 x 512 spinor workload (32 atoms) in FP32-mixed: steps/s, its roofline
                 and the adjoint/forward ratio of its recompute-mode adjoint step
+  large_gradient  dM_z/dtheta of its 8 pulse parameters through PulseMz (checkpoint every 25
+                steps in host memory, sub-segments of 5) over --large-gradient-steps steps:
+                forward and backward wall time and peak device memory (--large-gradient-fd: one
+                component against a fourth-order central difference)
   adjoint       adjoint/forward time ratio on the gradient workload (32^3 x 32, taped segments)
   ground_state  imaginary-time iterations/s of the headline workload
   cpu_baseline  the CPU oracle timed on this host (one ETRS step, scipy.fft on every core; and one
@@ -154,6 +158,74 @@ def cpu_baseline(w, budget_s: float = 45.0):
     return out
 
 
+def large_gradient(wl, nsteps, checkpoint_every, sub_every, fd):
+    """dM_z(T)/dtheta of the 8 pulse parameters on the large workload in FP32-mixed through
+    PulseMz with the two-level recompute schedule (checkpoints in host memory), timed; with fd,
+    one parameter (the largest component) against a fourth-order central difference of the same
+    trajectory."""
+    import numpy as np
+    import torch
+    from paper_2506_21908_amd import nct
+    pf = nct.NCT_FP32_MIXED
+    s = nct.system_from_workload(wl, precision=pf)
+    psi0 = nct.states_to_device(wl.psi0, pf)
+    pulses = wl.bfield.pulses
+    th0 = np.array([p.A for p in pulses] + [p.omega for p in pulses])
+    theta = torch.tensor(th0, dtype=torch.float64, requires_grad=True)
+    peak = [0.0]
+
+    def used():
+        f, t = torch.cuda.mem_get_info()
+        return (t - f) / 1e9
+
+    def prog(k, n):
+        peak[0] = max(peak[0], used())
+        say(f"large gradient: backward segment {k}/{n}")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = nct.pulse_mz(theta, s, psi0, pulses, nsteps, checkpoint_every, checkpoint_on_host=True,
+                     sub_every=sub_every, progress=prog)
+    torch.cuda.synchronize()
+    t_f = time.perf_counter() - t0
+    peak[0] = max(peak[0], used())
+    say(f"large gradient: {nsteps}-step forward in {t_f:.1f} s")
+    t0 = time.perf_counter()
+    L.backward()
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    g = theta.grad.numpy().copy()
+    out = {"workload": wl.name, "precision": "mixed", "steps": nsteps,
+           "checkpoint_every": checkpoint_every, "sub_every": sub_every,
+           "checkpoints": "host memory", "L_Mz": float(L.detach()),
+           "forward_s": t_f, "backward_s": t_b, "ratio": t_b / t_f,
+           "device_used_GB_peak": peak[0], "gradient": g.tolist(),
+           "definition": "backward wall time (segment and sub-segment re-runs, recompute-mode "
+                         "backward steps) / forward wall time of the same trajectory"}
+    if fd:
+        k = int(np.argmax(np.abs(g)))
+        h = 0.05 * abs(th0[k])
+
+        def L_at(dk):
+            th = th0.copy()
+            th[k] += dk
+            s.set_potentials(B0=(0.0, 0.0, 0.0), pulses=nct._pulses_with(pulses, th))
+            psi = psi0.clone()
+            s.step(psi, 0.0, nsteps)
+            tot = s.density_magnetization(psi, nsteps * wl.dt, totals=True)
+            say(f"large gradient: L at theta_{k} {dk:+.3e}: {tot[3]:.10f}")
+            return float(tot[3])
+
+        Lp1, Lm1, Lp2, Lm2 = L_at(h), L_at(-h), L_at(2 * h), L_at(-2 * h)
+        fd4 = (8.0 * (Lp1 - Lm1) - (Lp2 - Lm2)) / (12.0 * h)
+        out["fd_check"] = {"parameter": k, "h": h, "adjoint": float(g[k]), "central_difference_4th": fd4,
+                           "rel_diff": abs(g[k] - fd4) / abs(fd4)}
+    s.close()
+    del psi0
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +242,10 @@ def main():
     ap.add_argument("--no-ground-state", action="store_true", help="skip the ground-state timing")
     ap.add_argument("--no-large", action="store_true", help="skip the 96^3 x 512 FP32-mixed entry")
     ap.add_argument("--large-steps", type=int, default=10)
+    ap.add_argument("--large-gradient-steps", type=int, default=50,
+                    help="trajectory length of the large-workload pulse gradient (0: skip)")
+    ap.add_argument("--large-gradient-fd", action="store_true",
+                    help="check one gradient component against central differences")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain 1 GiB device copy first (PMC scale reference)")
     args = ap.parse_args()
@@ -413,7 +489,12 @@ def main():
             del psi, psi_n, lam
             torch.cuda.empty_cache()
         out["large"] = large
+        if args.large_gradient_steps > 0:
+            out["large_gradient"] = large_gradient(wl, args.large_gradient_steps, 25, 5,
+                                                   args.large_gradient_fd)
         del wl
+    elif case == 4 and args.large_gradient_steps > 0:
+        out["large_gradient"] = large_gradient(w, args.large_gradient_steps, 25, 5, args.large_gradient_fd)
 
     if not args.no_cpu_baseline:
         say("timing the oracle on the host cores")

@@ -7,6 +7,7 @@ there is no CPU fallback.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from ctypes import POINTER, c_double, c_int, c_void_p
 from typing import Optional, Sequence
@@ -378,6 +379,37 @@ def _pulses_with(pulses, theta):
     return out
 
 
+def _segment_adjoint_recompute(s, psi, t_c, n, dt, lam, grad, sub_every):
+    """Reverse sweep over one checkpointed segment of n steps without a multi-step tape: the
+    segment is re-run keeping its state every sub_every steps; each of those sub-segments is
+    re-run keeping the state of every step; then nct_backward_step runs step by step in recompute
+    mode (it re-runs its own step from psi_n with a one-step tape).  State sets held on the GPU:
+    n / sub_every sub-checkpoints and sub_every step states."""
+    subs = []
+    t = t_c
+    j0 = 0
+    while j0 < n:
+        m = min(sub_every, n - j0)
+        subs.append((psi.clone(), t, m))
+        if j0 + m < n:
+            s.step(psi, t, m)
+        t += m * dt
+        j0 += m
+    del psi
+    while subs:
+        psi_s, t_s, m = subs.pop()
+        states = [psi_s]
+        p = psi_s.clone()
+        for j in range(m - 1):
+            s.step(p, t_s + j * dt, 1)
+            states.append(p.clone())
+        del p
+        for j in reversed(range(m)):
+            s.backward_step(-1, states[j], t_s + j * dt, lam, lam, grad)
+            states[j] = None
+        del states, psi_s
+
+
 def _make_pulse_mz():
     import torch
 
@@ -386,18 +418,23 @@ def _make_pulse_mz():
         theta = (A_1..A_k, omega_1..omega_k) of the external field B_ext(t).
 
         forward: runs the trajectory with nct_step, keeping a copy of the states every
-        checkpoint_every steps.  backward: seeds lam = 2 dV f sigma_z psi_T
-        (nct_magnetization_seed), then for each segment in reverse re-runs it with the tape on
-        (nct_step(tape=1)) and calls nct_backward_step step by step; the library adds
-        dL/dB . dB/dtheta into the gradient.  The system's tape_steps must be >= checkpoint_every.
-        backward re-applies the field of its own forward call (theta and B0 are kept in ctx), so
-        other forward calls on the same system in between (finite differences, line searches)
-        do not change the gradient; the field the system held before backward is restored.
+        checkpoint_every steps (in host memory when checkpoint_on_host).  backward: seeds
+        lam = 2 dV f sigma_z psi_T (nct_magnetization_seed), then for each segment in reverse:
+        * if the system's tape holds a whole segment (tape_steps >= checkpoint_every), re-runs it
+          with the tape on (nct_step(tape=1)) and calls nct_backward_step step by step;
+        * otherwise (systems too large for a multi-step tape) takes the two-level schedule of
+          _segment_adjoint_recompute with sub-segments of sub_every steps (default about
+          sqrt(checkpoint_every)).
+        The library adds dL/dB . dB/dtheta into the gradient.  backward re-applies the field of its
+        own forward call (theta and B0 are kept in ctx), so other forward calls on the same system
+        in between (finite differences, line searches) do not change the gradient; the field the
+        system held before backward is restored.  progress, if given, is called as
+        progress(done_segments, total_segments) after each segment of the backward sweep.
         """
 
         @staticmethod
         def forward(ctx, theta, system, psi0, pulses, nsteps, checkpoint_every, t0=0.0,
-                    B0=(0.0, 0.0, 0.0)):
+                    B0=(0.0, 0.0, 0.0), checkpoint_on_host=False, sub_every=None, progress=None):
             th = theta.detach().cpu().double().numpy()
             system.set_potentials(B0=B0, pulses=_pulses_with(pulses, th))
             dt = float(system.params.dt)
@@ -407,7 +444,7 @@ def _make_pulse_mz():
             done = 0
             while done < nsteps:
                 n = min(int(checkpoint_every), nsteps - done)
-                ckpts.append((psi.clone(), t, n))
+                ckpts.append((psi.to("cpu") if checkpoint_on_host else psi.clone(), t, n))
                 system.step(psi, t, n)
                 t += n * dt
                 done += n
@@ -417,6 +454,8 @@ def _make_pulse_mz():
             ctx.psi_final = psi
             ctx.npar = 2 * len(pulses)
             ctx.field = (tuple(float(v) for v in B0), _pulses_with(pulses, th))
+            ctx.sub_every = int(sub_every) if sub_every else max(1, int(round(math.sqrt(checkpoint_every))))
+            ctx.progress = progress
             return torch.tensor(float(tot[3]), dtype=torch.float64)
 
         @staticmethod
@@ -429,15 +468,23 @@ def _make_pulse_mz():
                 lam = torch.empty_like(ctx.psi_final)
                 s.magnetization_seed(ctx.psi_final, (0.0, 0.0, 1.0), lam)
                 grad = np.zeros(ctx.npar)
-                for psi_c, t_c, n in reversed(ctx.ckpts):
-                    psi = psi_c.clone()
-                    s.step(psi, t_c, n, tape=True)
-                    for j in reversed(range(n)):
-                        s.backward_step(j, None, t_c + j * dt, lam, lam, grad)
+                taped = int(s.params.tape_steps) >= max(n for _, _, n in ctx.ckpts)
+                total = len(ctx.ckpts)
+                for k, (psi_c, t_c, n) in enumerate(reversed(ctx.ckpts)):
+                    psi = psi_c.to(ctx.psi_final.device).clone()
+                    if taped:
+                        s.step(psi, t_c, n, tape=True)
+                        for j in reversed(range(n)):
+                            s.backward_step(j, None, t_c + j * dt, lam, lam, grad)
+                    else:
+                        _segment_adjoint_recompute(s, psi, t_c, n, dt, lam, grad, ctx.sub_every)
+                    del psi
+                    if ctx.progress is not None:
+                        ctx.progress(k + 1, total)
             finally:
                 s.set_potentials(B0=held[0], pulses=held[1])
             g = torch.from_numpy(grad * float(gout))
-            return g, None, None, None, None, None, None, None
+            return g, None, None, None, None, None, None, None, None, None, None
 
     return PulseMz
 
@@ -445,9 +492,11 @@ def _make_pulse_mz():
 _PULSE_MZ = None
 
 
-def pulse_mz(theta, system, psi0, pulses, nsteps, checkpoint_every, t0=0.0, B0=(0.0, 0.0, 0.0)):
+def pulse_mz(theta, system, psi0, pulses, nsteps, checkpoint_every, t0=0.0, B0=(0.0, 0.0, 0.0),
+             checkpoint_on_host=False, sub_every=None, progress=None):
     """Differentiable final M_z with respect to the pulse parameters (see PulseMz)."""
     global _PULSE_MZ
     if _PULSE_MZ is None:
         _PULSE_MZ = _make_pulse_mz()
-    return _PULSE_MZ.apply(theta, system, psi0, pulses, nsteps, checkpoint_every, t0, B0)
+    return _PULSE_MZ.apply(theta, system, psi0, pulses, nsteps, checkpoint_every, t0, B0,
+                           checkpoint_on_host, sub_every, progress)

@@ -210,3 +210,34 @@ def test_pulse_gradient_backward_after_another_forward(torch_cuda):
     say(f"  adjoint {g}\n  oracle  {g_ref}")
     assert np.allclose(g, g_ref, rtol=1e-8, atol=1e-12 * np.max(np.abs(g_ref)))
     assert s.bfield_args[1] == held[1]
+
+
+def test_pulse_gradient_two_level_schedule(torch_cuda):
+    """The schedule for systems too large for a multi-step tape (host checkpoints every 6 steps,
+    sub-segments of 2, recompute-mode backward steps) gives the oracle's tangent-linear gradient
+    and the taped schedule's gradient."""
+    torch = torch_cuda
+    from paper_2506_21908_amd import nct
+    say("pulse gradient, two-level recompute schedule")
+    pulses = I.circular_pulses([0.1, 0.25], [0.5, 1.0], 0.05, 0.15)
+    w = I.make_system(n=(12, 12, 12), L=(7.0,) * 3, nstates=4, natoms=1, case=41,
+                      bfield=I.BField(pulses=pulses), full_spinors=False, xc=1)
+    nsteps = 13
+    g_ref = O.mz_gradient_tangent_linear(O.system_from_workload(w), w.psi0, nsteps)
+    th = [p.A for p in pulses] + [p.omega for p in pulses]
+    grads = {}
+    seen = []
+    for name, tape in (("taped", 6), ("recompute", 0)):
+        s = nct.system_from_workload(w, tape_steps=tape)
+        theta = torch.tensor(th, dtype=torch.float64, requires_grad=True)
+        L = nct.pulse_mz(theta, s, nct.states_to_device(w.psi0), pulses, nsteps, 6,
+                         checkpoint_on_host=(tape == 0), sub_every=2,
+                         progress=(lambda k, n: seen.append((k, n))) if tape == 0 else None)
+        L.backward()
+        grads[name] = theta.grad.numpy()
+        s.close()
+    say(f"  taped {grads['taped']}\n  recompute {grads['recompute']}\n  oracle {g_ref}")
+    assert seen == [(1, 3), (2, 3), (3, 3)]
+    scale = np.max(np.abs(g_ref))
+    assert np.allclose(grads["recompute"], g_ref, rtol=1e-8, atol=1e-12 * scale)
+    assert np.allclose(grads["recompute"], grads["taped"], rtol=1e-12, atol=1e-14 * scale)
