@@ -777,22 +777,29 @@ constexpr int xpass_tc(int nx) {
   return 16;
 }
 constexpr int XP_NT = 256;  // threads of the energy column pass
-// threads of the column pass per precision (tuning macros)
+// threads of the column pass per precision (tuning macros); FP32 tiles of 64 columns whose first
+// stage has at least 512 butterflies take NCT_XPASS_NT_F32_WIDE: at 64 points 512 threads
+// measured 4848 against 4571 GB/s (64^3 x 256), while the 48-point tile (384 butterflies) and
+// the 32-column tile at 96 points lost with 512 (4324 against 4402, 4256 against 4543 GB/s).
 #ifndef NCT_XPASS_NT_F64
 #define NCT_XPASS_NT_F64 256
 #endif
 #ifndef NCT_XPASS_NT_F32
 #define NCT_XPASS_NT_F32 256
 #endif
-template <typename R>
+#ifndef NCT_XPASS_NT_F32_WIDE
+#define NCT_XPASS_NT_F32_WIDE 512
+#endif
+template <typename R, int NX, int TC>
 __host__ __device__ constexpr int xp_nt() {
+  if constexpr (sizeof(R) == 4 && TC == 64 && TC * NX / plan_radix(NX, 0) >= 512) return NCT_XPASS_NT_F32_WIDE;
   return sizeof(R) == 8 ? NCT_XPASS_NT_F64 : NCT_XPASS_NT_F32;
 }
 
 // Column pass: one workgroup per tile of TC consecutive yz columns x NX planes of one batch
 // entry (spinor component).  The first forward x stage works on the values as they are loaded.
 template <typename R, int NX, int TC, int M>
-__global__ __launch_bounds__(xp_nt<R>()) void k_xpass(const cpx<R>* src, cpx<R>* dst, int NYZ,
+__global__ __launch_bounds__((xp_nt<R, NX, TC>())) void k_xpass(const cpx<R>* src, cpx<R>* dst, int NYZ,
                                                  const R* __restrict__ g2x,
                                                  const R* __restrict__ g2yz, R kscale, int mode,
                                                  const cpx<R>* __restrict__ twx_g, KTables<R> kt) {
@@ -802,7 +809,7 @@ __global__ __launch_bounds__(xp_nt<R>()) void k_xpass(const cpx<R>* src, cpx<R>*
   const int tiles = NYZ / TC;
   const int b = blockIdx.x / tiles;
   const int q0 = (blockIdx.x - b * tiles) * TC;
-  for (int k = tid; k < NX; k += xp_nt<R>()) tw[k] = twx_g[k];
+  for (int k = tid; k < NX; k += xp_nt<R, NX, TC>()) tw[k] = twx_g[k];
   const cpx<R>* srcb = src + size_t(b) * NX * NYZ + q0;
   cpx<R>* dstb = dst + size_t(b) * NX * NYZ + q0;
   {
@@ -810,17 +817,17 @@ __global__ __launch_bounds__(xp_nt<R>()) void k_xpass(const cpx<R>* src, cpx<R>*
     // factor as it writes back; the inverse DFT's last stage stores to dst
     constexpr int NS = plan_nstages(NX);
     if constexpr (NS > 1) {
-      stage_from<R, NX, 0, TC, 1, TC, 1, TC, xp_nt<R>(), true>(
+      stage_from<R, NX, 0, TC, 1, TC, 1, TC, xp_nt<R, NX, TC>(), true>(
           tile, tw, tid, [&](int e) { return ld_stream<M>(&srcb[size_t(e / TC) * NYZ + (e % TC)]); });
     } else {
-      for (int e = tid; e < NX * TC; e += xp_nt<R>()) tile[e] = ld_stream<M>(&srcb[size_t(e / TC) * NYZ + (e % TC)]);
+      for (int e = tid; e < NX * TC; e += xp_nt<R, NX, TC>()) tile[e] = ld_stream<M>(&srcb[size_t(e / TC) * NYZ + (e % TC)]);
       __syncthreads();
     }
     if constexpr (NS > 2) {
-      lds_stage<R, NX, 1, TC, 1, TC, true>(tile, tw, tid, xp_nt<R>());
+      lds_stage<R, NX, 1, TC, 1, TC, true>(tile, tw, tid, xp_nt<R, NX, TC>());
       __syncthreads();
     }
-    stage_to<R, NX, NS - 1, TC, 1, TC, 1, TC, xp_nt<R>(), true>(
+    stage_to<R, NX, NS - 1, TC, 1, TC, 1, TC, xp_nt<R, NX, TC>(), true>(
         tile, tw, tid, [](int) { return 0; }, [&](int e, int l, cpx<R> v, int) {
           R g;
           if (kt.kv) {  // |G + k|^2 of this spinor component's state
@@ -839,14 +846,14 @@ __global__ __launch_bounds__(xp_nt<R>()) void k_xpass(const cpx<R>* src, cpx<R>*
         });
     __syncthreads();
     if constexpr (NS > 2) {
-      lds_stage<R, NX, 2, TC, 1, TC, false>(tile, tw, tid, xp_nt<R>());
+      lds_stage<R, NX, 2, TC, 1, TC, false>(tile, tw, tid, xp_nt<R, NX, TC>());
       __syncthreads();
     }
     if constexpr (NS > 1) {
-      lds_stage<R, NX, 1, TC, 1, TC, false>(tile, tw, tid, xp_nt<R>());
+      lds_stage<R, NX, 1, TC, 1, TC, false>(tile, tw, tid, xp_nt<R, NX, TC>());
       __syncthreads();
     }
-    stage_to<R, NX, 0, TC, 1, TC, 1, TC, xp_nt<R>(), false>(
+    stage_to<R, NX, 0, TC, 1, TC, 1, TC, xp_nt<R, NX, TC>(), false>(
         tile, tw, tid, [](int) { return 0; }, [&](int e, int, cpx<R> v, int) {
           st_stream<M>(&dstb[size_t(e / TC) * NYZ + (e % TC)], v);
         });
@@ -1959,11 +1966,11 @@ static hipError_t launch_xpass_tc(int B, int NYZ, const void* src, void* dst, co
   // MI355X and costs occupancy)
   const dim3 grid(unsigned(B) * unsigned(tiles));
   if (cache_mode >= 2)
-    nct_launch((k_xpass<R, NX, TC, 2>), grid, dim3(xp_nt<R>()), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_, kt);
+    nct_launch((k_xpass<R, NX, TC, 2>), grid, dim3(xp_nt<R, NX, TC>()), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_, kt);
   else if (cache_mode == 1)
-    nct_launch((k_xpass<R, NX, TC, 1>), grid, dim3(xp_nt<R>()), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_, kt);
+    nct_launch((k_xpass<R, NX, TC, 1>), grid, dim3(xp_nt<R, NX, TC>()), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_, kt);
   else
-    nct_launch((k_xpass<R, NX, TC, 0>), grid, dim3(xp_nt<R>()), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_, kt);
+    nct_launch((k_xpass<R, NX, TC, 0>), grid, dim3(xp_nt<R, NX, TC>()), 0, st, s_, d_, NYZ, g2x, g2yz, kscale, mode, t_, kt);
   return hipGetLastError();
 }
 
