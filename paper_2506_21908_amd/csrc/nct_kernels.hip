@@ -761,12 +761,13 @@ __global__ __launch_bounds__(plane_nt(NY* NZ)) void k_plane_inv(const cpx<R>* in
 
 // ---------------------------------------------------------------- column pass along x
 // widest column-pass tile (64, 32, 16 columns) whose LDS footprint stays within a budget
-// (tuning macros, bytes per workgroup)
+// (tuning macros, bytes per workgroup).  FP32 at 96 points takes 64 columns (48 KB, three
+// 512-thread workgroups per CU): 4717 against 4535 GB/s with 32 columns (96^3 x 512).
 #ifndef NCT_XPASS_TILE_MAX_F64
 #define NCT_XPASS_TILE_MAX_F64 32768
 #endif
 #ifndef NCT_XPASS_TILE_MAX_F32
-#define NCT_XPASS_TILE_MAX_F32 32768
+#define NCT_XPASS_TILE_MAX_F32 49152
 #endif
 template <typename R>
 constexpr int xpass_tc(int nx) {
@@ -780,7 +781,8 @@ constexpr int XP_NT = 256;  // threads of the energy column pass
 // threads of the column pass per precision (tuning macros); FP32 tiles of 64 columns whose first
 // stage has at least 512 butterflies take NCT_XPASS_NT_F32_WIDE: at 64 points 512 threads
 // measured 4848 against 4571 GB/s (64^3 x 256), while the 48-point tile (384 butterflies) and
-// the 32-column tile at 96 points lost with 512 (4324 against 4402, 4256 against 4543 GB/s).
+// the 32-column tile at 96 points lost with 512 (4324 against 4402, 4256 against 4543 GB/s), and
+// the 64-column tile at 96 points with 256 (4159 against 4717 GB/s).
 #ifndef NCT_XPASS_NT_F64
 #define NCT_XPASS_NT_F64 256
 #endif
