@@ -477,8 +477,9 @@ __global__ __launch_bounds__(2 * plane2_nth<R>(NY* NZ), plane2_min_waves<R>(NY* 
 // Same stage as k_plane_stage2 for planes where two LDS planes would admit only one workgroup per
 // CU but one plane admits two (FP64 64^2: 67 KB; FP32 96^2: 76 KB).  The spinor components go
 // through the single LDS plane one after the other: the up component's kinetic part waits in
-// registers (PPT values per thread) while the down component is transformed; after the 2x2 update
-// the up result waits there again while the down result is finished and transformed forward.
+// registers (PPT values per thread, the last of them in a private LDS slot per thread) while the
+// down component is transformed; after the 2x2 update the up result waits there again while the
+// down result is finished and transformed forward.
 // Two resident workgroups per CU interleave their memory and transform phases.
 // Threads per workgroup (tuning macro) and the point batch of the 2x2 update.
 #ifndef NCT_PLANER_NT
@@ -495,6 +496,26 @@ constexpr bool planer_use() {
 #endif
 }
 
+// Values per thread of the held spinor component that live in LDS left over by the plane
+// (tuning macro NCT_PLANER_KL: at most that many, within the 80 KB of two workgroups per CU).
+// One slot takes four of the 128 VGPRs off the held values: FP64 64^2 spills 36 instead of 56 B
+// per lane and its plane pass runs 5707 instead of 5575 GB/s (64^3 x 256).
+#ifndef NCT_PLANER_KL
+#define NCT_PLANER_KL 1
+#endif
+template <typename R, int NY, int NZ>
+constexpr int planer_kl() {
+  constexpr size_t spare = 80 * 1024 - 512 - plane_lds_bytes<NY, NZ>(sizeof(cpx<R>));
+  constexpr int fit = int(spare / (size_t(NCT_PLANER_NT) * sizeof(cpx<R>)));
+  constexpr int ppt = (NY * NZ + NCT_PLANER_NT - 1) / NCT_PLANER_NT;
+  constexpr int kl = NCT_PLANER_KL < fit ? NCT_PLANER_KL : fit;
+  return kl < ppt ? kl : ppt;
+}
+template <typename R, int NY, int NZ>
+constexpr size_t planer_lds_bytes() {
+  return plane_lds_bytes<NY, NZ>(sizeof(cpx<R>)) + size_t(planer_kl<R, NY, NZ>()) * NCT_PLANER_NT * sizeof(cpx<R>);
+}
+
 template <typename R, int NY, int NZ, int M>
 __global__ __launch_bounds__(NCT_PLANER_NT, 4) void k_plane_stage_r(StageArgs<R> a, ProjTables pt,
                                                                      const cpx<R>* __restrict__ twy_g,
@@ -504,11 +525,16 @@ __global__ __launch_bounds__(NCT_PLANER_NT, 4) void k_plane_stage_r(StageArgs<R>
   constexpr int NT = NCT_PLANER_NT;
   constexpr int PZ = NZ + 1;
   constexpr int PPT = (NP + NT - 1) / NT;
-  constexpr int G = sizeof(R) == 8 ? 2 : 3;  // points per load batch of the 2x2 update
+  constexpr int KR = PPT - planer_kl<R, NY, NZ>();  // held values in registers, the rest in LDS
+#ifndef NCT_PLANER_G_F64  // points per load batch of the FP64 2x2 update (tuning macro)
+#define NCT_PLANER_G_F64 2
+#endif
+  constexpr int G = sizeof(R) == 8 ? NCT_PLANER_G_F64 : 3;  // points per load batch of the 2x2 update
   extern __shared__ double4 smem_d4[];
   cpx<R>* pl = reinterpret_cast<cpx<R>*>(smem_d4);
   cpx<R>* twy = pl + NY * PZ;
   cpx<R>* twz = twy + NY;
+  cpx<R>* kus = twz + NZ;  // [PPT - KR][NT]: each thread's own held values beyond KR
   const int tid = threadIdx.x;
   const int L = xcd_logical(blockIdx.x, gridDim.x);
   const int x = L / S;
@@ -520,13 +546,16 @@ __global__ __launch_bounds__(NCT_PLANER_NT, 4) void k_plane_stage_r(StageArgs<R>
   const size_t off1 = (size_t(2 * i + 1) * NX + x) * NP;
   const cpx<R>* __restrict__ tin = reinterpret_cast<const cpx<R>*>(a.tmp_in);
 
-  // 1) kinetic part of the up component (inverse 2D transform), kept in registers
+  // 1) kinetic part of the up component (inverse 2D transform), kept in registers (the first KR
+  //    values of each thread) and in the thread's own LDS slots (the rest)
   plane_fft_inv_from<R, NY, NZ, PZ, NT>(pl, twy, twz, tid, [&](int g) { return ld_stream<M>(&tin[off0 + g]); });
-  cpx<R> ku[PPT];
+  cpx<R> ku[KR > 0 ? KR : 1];
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
     const int e = min(tid + j * NT, NP - 1);
-    ku[j] = pl[(e / NZ) * PZ + (e % NZ)];
+    const cpx<R> v = pl[(e / NZ) * PZ + (e % NZ)];
+    if (j < KR) ku[j < KR ? j : 0] = v;
+    else kus[(j - KR) * NT + tid] = v;
   }
   __syncthreads();
   // 2) kinetic part of the down component, left in LDS
@@ -569,7 +598,7 @@ __global__ __launch_bounds__(NCT_PLANER_NT, 4) void k_plane_stage_r(StageArgs<R>
         const int e = tid + j * NT;
         if (j < PPT && e < NP) {
           const int q = (e / NZ) * PZ + (e % NZ);
-          const cpx<R> tu = ku[j], td = pl[q];
+          const cpx<R> tu = j < KR ? ku[j < KR ? j : 0] : kus[(j - KR) * NT + tid], td = pl[q];
           const R v = fv[g] + (lx + a.lg[1] * R(e / NZ) + a.lg[2] * R(e % NZ));
           const R bx = fx[g] + a.bext[0], by = fy[g] + a.bext[1], bz = fz[g] + a.bext[2];
           cpx<R> hu, hd;
@@ -585,7 +614,8 @@ __global__ __launch_bounds__(NCT_PLANER_NT, 4) void k_plane_stage_r(StageArgs<R>
             od.x += a.alpha * xd[g].x;
             od.y += a.alpha * xd[g].y;
           }
-          ku[j] = ou;
+          if (j < KR) ku[j < KR ? j : 0] = ou;
+          else kus[(j - KR) * NT + tid] = ou;
           pl[q] = od;
         }
       }
@@ -620,7 +650,7 @@ __global__ __launch_bounds__(NCT_PLANER_NT, 4) void k_plane_stage_r(StageArgs<R>
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
         const int e = tid + j * NT;
-        if (e < NP) pl[(e / NZ) * PZ + (e % NZ)] = ku[j];
+        if (e < NP) pl[(e / NZ) * PZ + (e % NZ)] = j < KR ? ku[j < KR ? j : 0] : kus[(j - KR) * NT + tid];
       }
       __syncthreads();
     }
@@ -792,9 +822,13 @@ constexpr int XP_NT = 256;  // threads of the energy column pass
 #ifndef NCT_XPASS_NT_F32_WIDE
 #define NCT_XPASS_NT_F32_WIDE 512
 #endif
+#ifndef NCT_XPASS_NT_F64_WIDE
+#define NCT_XPASS_NT_F64_WIDE 512
+#endif
 template <typename R, int NX, int TC>
 __host__ __device__ constexpr int xp_nt() {
   if constexpr (sizeof(R) == 4 && TC == 64 && TC * NX / plan_radix(NX, 0) >= 512) return NCT_XPASS_NT_F32_WIDE;
+  if constexpr (sizeof(R) == 8 && TC == 64 && TC * NX / plan_radix(NX, 0) >= 512) return NCT_XPASS_NT_F64_WIDE;
   return sizeof(R) == 8 ? NCT_XPASS_NT_F64 : NCT_XPASS_NT_F32;
 }
 
@@ -1835,7 +1869,7 @@ static hipError_t launch_plane_stage_m(int S, int NX, const StageArgs<R>& a, con
   const auto ty = reinterpret_cast<const cpx<R>*>(twy);
   const auto tz = reinterpret_cast<const cpx<R>*>(twz);
   if constexpr (planer_use<R, A, B>()) {
-    constexpr size_t ldsr = plane_lds_bytes<A, B>(sizeof(cpx<R>));
+    constexpr size_t ldsr = planer_lds_bytes<R, A, B>();
     auto kernr = k_plane_stage_r<R, A, B, M>;
     hipError_t er = set_lds(kernr, ldsr);
     if (er != hipSuccess) return er;
