@@ -812,7 +812,9 @@ constexpr int XP_NT = 256;  // threads of the energy column pass
 // stage has at least 512 butterflies take NCT_XPASS_NT_F32_WIDE: at 64 points 512 threads
 // measured 4848 against 4571 GB/s (64^3 x 256), while the 48-point tile (384 butterflies) and
 // the 32-column tile at 96 points lost with 512 (4324 against 4402, 4256 against 4543 GB/s), and
-// the 64-column tile at 96 points with 256 (4159 against 4717 GB/s).
+// the 64-column tile at 96 points with 256 (4159 against 4717 GB/s).  FP64 at 64 points keeps 32
+// columns: a 64-column tile (64 KB, two workgroups per CU) measured 4940 GB/s with 512 threads and
+// 4630 with 256, against 4960.
 #ifndef NCT_XPASS_NT_F64
 #define NCT_XPASS_NT_F64 256
 #endif
@@ -822,13 +824,9 @@ constexpr int XP_NT = 256;  // threads of the energy column pass
 #ifndef NCT_XPASS_NT_F32_WIDE
 #define NCT_XPASS_NT_F32_WIDE 512
 #endif
-#ifndef NCT_XPASS_NT_F64_WIDE
-#define NCT_XPASS_NT_F64_WIDE 512
-#endif
 template <typename R, int NX, int TC>
 __host__ __device__ constexpr int xp_nt() {
   if constexpr (sizeof(R) == 4 && TC == 64 && TC * NX / plan_radix(NX, 0) >= 512) return NCT_XPASS_NT_F32_WIDE;
-  if constexpr (sizeof(R) == 8 && TC == 64 && TC * NX / plan_radix(NX, 0) >= 512) return NCT_XPASS_NT_F64_WIDE;
   return sizeof(R) == 8 ? NCT_XPASS_NT_F64 : NCT_XPASS_NT_F32;
 }
 
