@@ -201,10 +201,11 @@ __host__ __device__ constexpr int plan_span(int N, int s) {
 // ---------------------------------------------------------------- one LDS stage
 // NCT_TW_PRODUCTS (tuning macro): FP64 radix-8 butterflies read w1, w2 and w4 (1), w1 and w2 (2)
 // or w1 (3) from the table and form the other twiddles as products (at most three roundings).
-// Fewer values in flight: the FP64 64^2 plane pass spills 56 instead of 72 B per lane and runs
-// 5575 instead of 5455 GB/s (64^3 x 256); the FP64 48^2 one no longer spills.
+// Fewer values in flight: with three reads the FP64 64^2 plane pass spilled 56 instead of 72 B
+// per lane and ran 5575 instead of 5455 GB/s (64^3 x 256), and the FP64 48^2 one no longer
+// spills; two reads are what leave the forward FP64 64^2 kernel without spill.
 #ifndef NCT_TW_PRODUCTS
-#define NCT_TW_PRODUCTS 1
+#define NCT_TW_PRODUCTS 2
 #endif
 // Butterfly of stage STAGE on its RAD operands x (in place); b: index within the stage's block,
 // tw[e] = exp(-2 pi i e / N).  Forward (DIF): DFT then twiddles; inverse (DIT): conjugate

@@ -516,7 +516,8 @@ constexpr size_t planer_lds_bytes() {
   return plane_lds_bytes<NY, NZ>(sizeof(cpx<R>)) + size_t(planer_kl<R, NY, NZ>()) * NCT_PLANER_NT * sizeof(cpx<R>);
 }
 
-template <typename R, int NY, int NZ, int M>
+// ACC: the kernel carries the adjoint's accumulation acc += w_out (only the adjoint passes acc).
+template <typename R, int NY, int NZ, int M, bool ACC>
 __global__ __launch_bounds__(NCT_PLANER_NT, 4) void k_plane_stage_r(StageArgs<R> a, ProjTables pt,
                                                                      const cpx<R>* __restrict__ twy_g,
                                                                      const cpx<R>* __restrict__ twz_g,
@@ -680,7 +681,7 @@ __global__ __launch_bounds__(NCT_PLANER_NT, 4) void k_plane_stage_r(StageArgs<R>
         }
       }
     }
-    if (acc) {
+    if (ACC && acc) {
       cpx<R> v[PPT];
 #pragma unroll
       for (int j = 0; j < PPT; ++j) v[j] = acc[offh + min(tid + j * NT, NP - 1)];
@@ -1868,7 +1869,14 @@ static hipError_t launch_plane_stage_m(int S, int NX, const StageArgs<R>& a, con
   const auto tz = reinterpret_cast<const cpx<R>*>(twz);
   if constexpr (planer_use<R, A, B>()) {
     constexpr size_t ldsr = planer_lds_bytes<R, A, B>();
-    auto kernr = k_plane_stage_r<R, A, B, M>;
+    // FP64 stages without accumulation take an instantiation without that path: four fewer
+    // live values leave the FP64 64^2 kernel without register spill.  FP32 keeps one
+    // instantiation: without the path the compiler allocates the FP32 96^2 kernel worse (36 B of
+    // spill per lane instead of 28).
+    auto kernr = k_plane_stage_r<R, A, B, M, true>;
+    if constexpr (sizeof(R) == 8) {
+      if (!a.acc) kernr = k_plane_stage_r<R, A, B, M, false>;
+    }
     hipError_t er = set_lds(kernr, ldsr);
     if (er != hipSuccess) return er;
     nct_launch(kernr, dim3(grid), dim3(NCT_PLANER_NT), ldsr, st, a, pt, ty, tz, S, NX);
